@@ -1,0 +1,264 @@
+"""CPU oracle for the Wilson-Dirac multi-mass solve: TEST INFRASTRUCTURE ONLY.
+
+Plain FP64 reference implementation (C library `liboracle.so` plus small numpy helpers) of
+what the GPU path computes. Only `tests/`, `__graft_entry__.smoke()` and the benchmark's
+`cpu_baseline` leg may import it; the GPU package never does, and the two share no code.
+
+Layout: lexicographic, x fastest. Gauge U[4][T][Z][Y][X][3][3], fermions psi[T][Z][Y][X][3][4],
+complex128. M(kappa) is the paper's M(m;U) with m*a + 4 = 1/(2 kappa) (Sec. 2, eq. 3).
+
+Functions and the passages they follow:
+  apply / hopping           Sec. 2, eq. 3 and eq. 4 (full 4x4 spin matrices)
+  mprec / eo_source /
+  eo_reconstruct            Sec. 6.2.3, eq. eo2-eo4
+  bicgstab / bicgstab_eo    van der Vorst's BiCGstab (cited in Sec. 6), update x <- x - beta s + chi w (Sec. 5)
+  bicgstab_m                BiCGstab-M (Jegerlehner, cited in Sec. 6.1), base = most singular mass,
+                            frozen shifts (Sec. 6.1)
+  poly_weights              Lagrange form of the Vandermonde solve (Sec. 6.2.1)
+  multimass_sequential      heaviest mass first, highest-order polynomial guess (Sec. 7)
+  gauge_grad / su3_project  derivative of Re<eta, M^{-1} b> with respect to the links
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+STATUS_OK = 0
+STATUS_NOCONV = 4
+STATUS_BREAKDOWN = 5
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIBPATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_LIBPATH)
+        L.oracle_gamma.argtypes = [ctypes.c_int, _D]
+        L.oracle_hopping.argtypes = [_I, ctypes.c_int, _D, _D, _D, ctypes.c_int]
+        L.oracle_apply.argtypes = [_I, ctypes.c_int, _D, ctypes.c_double, _D, _D, ctypes.c_int]
+        L.oracle_mprec.argtypes = [_I, ctypes.c_int, _D, ctypes.c_double, _D, _D, ctypes.c_int]
+        L.oracle_eo_source.argtypes = [_I, ctypes.c_int, _D, ctypes.c_double, _D, _D]
+        L.oracle_eo_reconstruct.argtypes = [_I, ctypes.c_int, _D, ctypes.c_double, _D, _D]
+        L.oracle_bicgstab.argtypes = [_I, ctypes.c_int, _D, ctypes.c_double, _D, _D, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int, _I, _D]
+        L.oracle_bicgstab.restype = ctypes.c_int
+        L.oracle_bicgstab_eo.argtypes = L.oracle_bicgstab.argtypes
+        L.oracle_bicgstab_eo.restype = ctypes.c_int
+        L.oracle_bicgstab_m.argtypes = [_I, ctypes.c_int, _D, ctypes.c_int, _D, _D, _D, ctypes.c_double,
+                                        ctypes.c_int, _I, _I]
+        L.oracle_bicgstab_m.restype = ctypes.c_int
+        L.oracle_gauge_grad.argtypes = [_I, ctypes.c_int, _D, _D, _D]
+        L.oracle_parity.argtypes = [_I, ctypes.c_long]
+        L.oracle_parity.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_get_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def set_threads(n: int) -> None:
+    lib().oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().oracle_get_threads())
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D)
+
+
+def _dims_of_links(U):
+    assert U.ndim == 7 and U.shape[0] == 4 and U.shape[-2:] == (3, 3)
+    T, Z, Y, X = U.shape[1:5]
+    return (X, Y, Z, T)
+
+
+def _dims_arr(dims):
+    return (ctypes.c_int * 4)(*dims)
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def gamma(mu: int) -> np.ndarray:
+    """gamma_mu (mu = 0..3 for the paper's 1..4) in the chiral basis of Sec. 2."""
+    out = np.zeros((4, 4), dtype=np.complex128)
+    lib().oracle_gamma(mu, _dp(out))
+    return out
+
+
+def hopping(U, psi, dag=False, antiperiodic=True):
+    """sum over the 8 directions of T_mu psi (the bracket of eq. 3 without the -1/2)."""
+    U = _c128(U)
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    lib().oracle_hopping(_dims_arr(_dims_of_links(U)), int(antiperiodic), _dp(U), _dp(psi), _dp(out), int(dag))
+    return out
+
+
+def apply(U, kappa, psi, dag=False, antiperiodic=True):
+    """M(kappa) psi, or M(kappa)^dag psi (eq. 3)."""
+    U = _c128(U)
+    psi = _c128(psi)
+    out = np.empty_like(psi)
+    lib().oracle_apply(_dims_arr(_dims_of_links(U)), int(antiperiodic), _dp(U), float(kappa), _dp(psi), _dp(out),
+                       int(dag))
+    return out
+
+
+def parity_mask(dims):
+    """Boolean [T, Z, Y, X] array, True on odd sites (parity of x+y+z+t, Sec. 6.2.3)."""
+    X, Y, Z, T = dims
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    return ((x + y + z + t) % 2) == 1
+
+
+def mprec(U, kappa, psi_e, dag=False, antiperiodic=True):
+    """M_prec psi_e on full-length fields (odd sites of psi_e ignored, zero on return), eq. eo4."""
+    U = _c128(U)
+    psi = _c128(psi_e)
+    out = np.empty_like(psi)
+    lib().oracle_mprec(_dims_arr(_dims_of_links(U)), int(antiperiodic), _dp(U), float(kappa), _dp(psi), _dp(out),
+                       int(dag))
+    return out
+
+
+def eo_source(U, kappa, b, antiperiodic=True):
+    U = _c128(U)
+    b = _c128(b)
+    out = np.empty_like(b)
+    lib().oracle_eo_source(_dims_arr(_dims_of_links(U)), int(antiperiodic), _dp(U), float(kappa), _dp(b), _dp(out))
+    return out
+
+
+def eo_reconstruct(U, kappa, b, x_even, antiperiodic=True):
+    U = _c128(U)
+    b = _c128(b)
+    x = _c128(x_even).copy()
+    lib().oracle_eo_reconstruct(_dims_arr(_dims_of_links(U)), int(antiperiodic), _dp(U), float(kappa), _dp(b),
+                                _dp(x))
+    return x
+
+
+def bicgstab(U, kappa, b, tol=1e-10, maxit=10000, x0=None, antiperiodic=True, eo=False):
+    """Solve M(kappa) x = b; returns (x, iterations, status, relative-residual history)."""
+    U = _c128(U)
+    b = _c128(b)
+    x = np.zeros_like(b) if x0 is None else _c128(x0).copy()
+    it = ctypes.c_int(0)
+    hist = np.zeros(maxit + 1)
+    fn = lib().oracle_bicgstab_eo if eo else lib().oracle_bicgstab
+    st = fn(_dims_arr(_dims_of_links(U)), int(antiperiodic), _dp(U), float(kappa), _dp(b), _dp(x), float(tol),
+            int(maxit), int(x0 is not None), ctypes.byref(it), _dp(hist))
+    return x, it.value, st, hist[: it.value].copy()
+
+
+def bicgstab_eo(U, kappa, b, tol=1e-10, maxit=10000, x0=None, antiperiodic=True):
+    return bicgstab(U, kappa, b, tol, maxit, x0, antiperiodic, eo=True)
+
+
+def bicgstab_m(U, kappas, b, tol=1e-10, maxit=10000, antiperiodic=True):
+    """Multi-shift BiCGstab-M; returns (list of x_i in the order of kappas, iterations, status, freeze iterations)."""
+    U = _c128(U)
+    b = _c128(b)
+    k = np.ascontiguousarray(kappas, dtype=np.float64)
+    nk = len(k)
+    assert 1 <= nk <= 64
+    xs = np.zeros((nk,) + b.shape, dtype=np.complex128)
+    it = ctypes.c_int(0)
+    conv = (ctypes.c_int * nk)()
+    st = lib().oracle_bicgstab_m(_dims_arr(_dims_of_links(U)), int(antiperiodic), _dp(U), nk, _dp(k), _dp(b), _dp(xs),
+                                 float(tol), int(maxit), ctypes.byref(it), conv)
+    return [xs[i] for i in range(nk)], it.value, st, list(conv)
+
+
+def true_residual(U, kappa, x, b, antiperiodic=True):
+    """|b - M x| / |b| in FP64."""
+    r = b - apply(U, kappa, x, antiperiodic=antiperiodic)
+    return float(np.linalg.norm(r) / np.linalg.norm(b))
+
+
+def mass_of_kappa(kappa):
+    """m a = 1/(2 kappa) - 4."""
+    return 1.0 / (2.0 * np.asarray(kappa, dtype=np.float64)) - 4.0
+
+
+def poly_weights(m_prev, m_new):
+    """Lagrange weights c_j = prod_{i != j} (m - m_i)/(m_j - m_i) (Sec. 6.2.1), so that the
+    extrapolated guess is psi(m) = sum_j c_j psi_j."""
+    m_prev = [float(v) for v in m_prev]
+    c = []
+    for j, mj in enumerate(m_prev):
+        w = 1.0
+        for i, mi in enumerate(m_prev):
+            if i != j:
+                w *= (m_new - mi) / (mj - mi)
+        c.append(w)
+    return c
+
+
+def multimass_sequential(U, kappas, b, tol=1e-10, maxit=10000, guess="poly", eo=True, antiperiodic=True):
+    """Single-mass BiCGstab once per mass, heaviest mass (smallest kappa) first; with
+    guess='poly' each start vector is the highest-order Lagrange extrapolation in m a of the
+    solutions found so far (Sec. 6.2.1, Sec. 7). Returns (solutions in the caller's order,
+    iteration counts in the caller's order)."""
+    order = sorted(range(len(kappas)), key=lambda i: kappas[i])
+    sols, its = [None] * len(kappas), [0] * len(kappas)
+    done_m, done_x = [], []
+    for i in order:
+        x0 = None
+        m = float(mass_of_kappa(kappas[i]))
+        if guess == "poly" and done_x:
+            c = poly_weights(done_m, m)
+            x0 = sum(cj * xj for cj, xj in zip(c, done_x))
+        x, it, st, _ = bicgstab(U, kappas[i], b, tol, maxit, x0=x0, antiperiodic=antiperiodic, eo=eo)
+        sols[i], its[i] = x, it
+        done_m.append(m)
+        done_x.append(x)
+    return sols, its
+
+
+def gauge_grad(x, lam, antiperiodic=True):
+    """G_mu(n) = dL/dRe U + i dL/dIm U for L = Re<eta, M^{-1} b>, given x = M^{-1} b and
+    lam = M^{-dag} eta; shape [4, T, Z, Y, X, 3, 3]."""
+    x = _c128(x)
+    lam = _c128(lam)
+    T, Z, Y, X = x.shape[:4]
+    G = np.empty((4, T, Z, Y, X, 3, 3), dtype=np.complex128)
+    lib().oracle_gauge_grad(_dims_arr((X, Y, Z, T)), int(antiperiodic), _dp(x), _dp(lam), _dp(G))
+    return G
+
+
+def su3_project(U, G):
+    """F = (i/2) TA(U G^dag), TA(Y) = (Y - Y^dag)/2 - tr(Y - Y^dag)/6. For U -> exp(i e_a T_a) U
+    with Hermitian traceless generators T_a, dL/de_a = 2 tr(T_a F)."""
+    Y = np.einsum("...ab,...cb->...ac", U, np.conj(G))
+    A = 0.5 * (Y - np.conj(np.swapaxes(Y, -1, -2)))
+    tr = np.trace(A, axis1=-2, axis2=-1)[..., None, None] / 3.0
+    return 0.5j * (A - tr * np.eye(3))
+
+
+def dense_matrix(U, kappa, antiperiodic=True):
+    """Dense M(kappa) built column by column from the oracle operator (tiny lattices only)."""
+    T, Z, Y, X = U.shape[1:5]
+    n = X * Y * Z * T * 12
+    Mdense = np.empty((n, n), dtype=np.complex128)
+    e = np.zeros(n, dtype=np.complex128)
+    for j in range(n):
+        e[:] = 0
+        e[j] = 1
+        Mdense[:, j] = apply(U, kappa, e.reshape(T, Z, Y, X, 3, 4), antiperiodic=antiperiodic).ravel()
+    return Mdense
