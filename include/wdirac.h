@@ -1,0 +1,196 @@
+/*
+ * wdirac: Wilson-Dirac multi-mass BiCGstab solves on one AMD MI355X (gfx950).
+ *
+ * C ABI of libwdirac.so. Every entry point takes plain device pointers and sizes; no C++ or
+ * framework types cross the boundary, and no exception escapes it.
+ *
+ * Paper: A. Alexandru, C. Pelissier, B. Gamari, F. Lee, "Multi-mass solvers for lattice QCD on GPUs".
+ *
+ * Conventions shared by every call
+ * ---------------------------------
+ * Lattice: extents X, Y, Z, T (dims[0..3]), all even and >= 2. Site order is x fastest:
+ *   n = x + X*(y + Y*(z + Z*t)).  Directions mu = 0,1,2,3 are x,y,z,t (the paper's 1..4).
+ *   Space is periodic; time is antiperiodic when geom.antiperiodic_t = 1 (periodic when 0).
+ * Fermion field (paper Sec. 2, after eq. 3): 12 complex numbers per site, a 3x4 colour-by-spin
+ *   matrix; device array of interleaved complex128 (double re, double im), shape [V][3][4],
+ *   i.e. 24 doubles per site, colour major, spin minor. V = X*Y*Z*T.
+ * Gauge field (Sec. 2, eq. 4): U_mu(n), the SU(3) link from n to n+mu; device array of complex128,
+ *   shape [4][V][3][3] (mu, site, row, column).
+ * Operator (Sec. 2, eq. 3 and eq. 4) with the paper's mass written through kappa,
+ *   m a + 4 = 1/(2 kappa):
+ *     (M psi)_n = psi_n/(2 kappa) - 1/2 sum_mu [ U_mu(n) psi_{n+mu} (1 - gamma_mu)
+ *                                            + U_mu(n-mu)^dag psi_{n-mu} (1 + gamma_mu) ]
+ *   with the chiral gamma matrices of Sec. 2 multiplying the 3x4 site matrix from the right, and
+ *   a factor -1 on the time hops that cross the t boundary when antiperiodic.
+ *   M^dag = gamma5 M gamma5, gamma5 = diag(1, 1, -1, -1) on the spin index.
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the default stream). Every kernel is
+ *   launched on it. wd_apply, wd_apply_dag and wd_gauge_grad are asynchronous; the solvers
+ *   return after the solve has finished (they synchronise the stream).
+ * Ownership: the caller owns every field buffer (allocate and free them yourself, e.g. with
+ *   torch). The library owns wd_gauge handles and their workspaces: created by
+ *   wd_gauge_create, released by wd_gauge_destroy. A handle may be used from one host thread at
+ *   a time; calls on one handle must not overlap.
+ * Errors: every call returns a wd_status. WD_OK on success. On failure nothing is thrown;
+ *   wd_last_error gives a thread-local message. Device pointers are not dereferenced on the
+ *   host; NULL pointers and misaligned pointers (not 16-byte aligned) give WD_ERR_ARG.
+ */
+#ifndef WDIRAC_H
+#define WDIRAC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WD_OK = 0,
+    WD_ERR_ARG = 1,         /* invalid argument (shape, pointer, parameter)            */
+    WD_ERR_HIP = 2,         /* a HIP runtime call failed                               */
+    WD_ERR_OOM = 3,         /* device allocation failed                                */
+    WD_ERR_NOCONV = 4,      /* max_iter reached; x holds the last iterate, stats filled */
+    WD_ERR_BREAKDOWN = 5,   /* BiCGstab breakdown (<rhat, A s> or chi vanished) after one restart */
+    WD_ERR_NAN = 6,         /* a NaN or Inf appeared in the iteration                   */
+    WD_ERR_UNSUPPORTED = 7  /* combination of options not implemented                   */
+} wd_status;
+
+typedef enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2, WD_BF16 = 3 } wd_prec;
+
+typedef struct {
+    int dims[4];        /* X, Y, Z, T: all even, >= 2 */
+    int antiperiodic_t; /* 1: antiperiodic in time (default), 0: periodic */
+} wd_geom;
+
+typedef struct wd_gauge wd_gauge; /* opaque: geometry, packed links, workspaces */
+
+typedef struct {
+    double tol;            /* stop when |b - M x| < tol |b| (Sec. 6.1 exit criterion)                   */
+    int max_iter;          /* iteration cap (per mass for sequential solves)                           */
+    int mixed;             /* 0: FP64 throughout. 1: iterate with low-precision storage and FP32
+                              arithmetic, FP64 reductions, FP64 reliable updates of x and r             */
+    wd_prec spinor_store;  /* storage of the iterated vectors when mixed: WD_F32 or WD_F16             */
+    wd_prec link_store;    /* storage of the links of the low-precision operator: WD_F32, WD_F16,
+                              WD_BF16                                                                  */
+    int recon;             /* link format of the low-precision operator: 12 (two rows stored, third
+                              rebuilt from unitarity) or 18                                            */
+    int eo;                /* 1: even-odd preconditioning (Sec. 6.2.3); single-mass solves only       */
+    double delta_reliable; /* mixed: reliable update once |r| < delta * max|r| since the last one     */
+    int use_x0;            /* 1: x holds the start vector on entry (single-mass solves only)          */
+    int dagger;            /* 1: solve M^dag x = b instead, through M^dag = gamma5 M gamma5            */
+} wd_solver_params;
+
+typedef struct {
+    int iters;             /* Krylov iterations                                                    */
+    int reliable_updates;  /* FP64 residual recomputations (mixed mode)                            */
+    int status;            /* wd_status of this system                                             */
+    double true_rel_res;   /* |b - M x| / |b| recomputed in FP64 after the solve                   */
+    double seconds;        /* wall time of this system's solve (shared wall time for joint solves) */
+} wd_solver_stats;
+
+typedef struct {
+    wd_gauge* gauge;   /* lattice and links of this system          */
+    double kappa;      /* mass parameter                            */
+    const double* b;   /* device, [V][3][4] complex128 source       */
+    double* x;         /* device, [V][3][4] complex128 solution     */
+} wd_system;
+
+enum { WD_METHOD_SEQUENTIAL = 0, WD_METHOD_MULTISHIFT = 1 };
+enum { WD_GUESS_NONE = 0, WD_GUESS_POLY = 1 };
+
+/* Defaults: tol 1e-8, max_iter 5000, mixed 1, F32 spinors, F16 links, recon 12, eo 1,
+   delta_reliable 0.1, use_x0 0, dagger 0. */
+void wd_params_default(wd_solver_params* p);
+
+/*
+ * Build a handle for one lattice and gauge field (Sec. 4, eq. 8 describes the paper's link
+ * layout; the handle stores its own layout). U: device pointer, complex128 [4][V][3][3], read
+ * during the call only (it may be freed afterwards). storage_hint (may be NULL): low-precision
+ * link formats to build now; others are built on first use.
+ * Errors: WD_ERR_ARG for odd or < 2 extents or NULL pointers, WD_ERR_OOM, WD_ERR_HIP.
+ */
+wd_status wd_gauge_create(wd_gauge** g, const wd_geom* geom, const double* U,
+                          const wd_solver_params* storage_hint, void* stream);
+wd_status wd_gauge_destroy(wd_gauge* g);
+
+/* out = M(kappa) in  (Sec. 2, eq. 3 and 4; FP64). in, out: device [V][3][4] complex128, distinct. */
+wd_status wd_apply(wd_gauge* g, double kappa, double* out, const double* in, void* stream);
+/* out = M(kappa)^dag in = gamma5 M gamma5 in (FP64). */
+wd_status wd_apply_dag(wd_gauge* g, double kappa, double* out, const double* in, void* stream);
+
+/*
+ * Single-mass BiCGstab for M(kappa) x = b (van der Vorst's method, cited in Sec. 6; the solution
+ * update x <- x - beta s + chi w of Sec. 5). With params->eo the even-odd system of Sec. 6.2.3
+ * (eq. eo2-eo4) is solved and the odd half rebuilt from eq. eo3. With params->mixed the
+ * iteration runs with low-precision storage and FP64 reliable updates, which recompute the true
+ * residual inside one Krylov run instead of restarting an inner solve as the paper's
+ * defect-correction scheme does (Sec. 6.2.4).
+ * x, b: device [V][3][4] complex128. stats (may be NULL): filled on return, also on NOCONV.
+ * Returns WD_OK, WD_ERR_NOCONV (x holds the last iterate), WD_ERR_BREAKDOWN, WD_ERR_NAN, ...
+ */
+wd_status bicgstab_solve(wd_gauge* g, double kappa, double* x, const double* b,
+                         const wd_solver_params* params, wd_solver_stats* stats, void* stream);
+
+/*
+ * Multi-shift BiCGstab-M (Jegerlehner, cited in Sec. 6.1) for M(kappa_i) x_i = b, i < n, FP64,
+ * full lattice, zero start vectors (the paper notes even-odd preconditioning, mixed precision and
+ * start guesses do not apply). The unshifted system is the most singular one (largest kappa);
+ * each shifted system stops being updated once it has converged; the solve stops when the
+ * unshifted residual satisfies |r| < tol |b| (Sec. 6.1). x: host array of n device pointers.
+ * stats: host array of n entries (may be NULL). 1 <= n <= 32.
+ */
+wd_status bicgstab_m_solve(wd_gauge* g, int n, const double* kappas, double* const* x, const double* b,
+                           const wd_solver_params* params, wd_solver_stats* stats, void* stream);
+
+/*
+ * Multi-mass driver (Sec. 6, eq. 6.1; Sec. 7). method WD_METHOD_SEQUENTIAL: single-mass BiCGstab
+ * once per mass, heaviest mass (smallest kappa) first; with WD_GUESS_POLY each start vector is the
+ * highest-order Lagrange extrapolation in m a of the solutions found so far (Sec. 6.2.1).
+ * method WD_METHOD_MULTISHIFT: one bicgstab_m_solve. 1 <= n <= 32.
+ */
+wd_status wd_multimass_solve(wd_gauge* g, int n, const double* kappas, double* const* x, const double* b,
+                             int method, int guess, const wd_solver_params* params,
+                             wd_solver_stats* stats, void* stream);
+
+/*
+ * Batched single-mass solves: nsys independent systems (any mix of handles, lattices, kappas and
+ * sources) iterate together, one kernel launch per solver step for all of them; converged
+ * systems drop out. Even-odd preconditioning is required (params->eo = 1). sys: host array.
+ * stats: host array of nsys entries (may be NULL). 1 <= nsys <= 1024.
+ */
+wd_status wd_batch_solve(int nsys, const wd_system* sys, const wd_solver_params* params,
+                         wd_solver_stats* stats, void* stream);
+
+/*
+ * Link derivative of L = Re <eta, M(kappa)^{-1} b> given x = M^{-1} b and lam = M^{-dag} eta
+ * (obtained by differentiating eq. 3/4 with respect to U):
+ *   G_mu(n) = 1/2 s [ lam_n (1 - gamma_mu) x_{n+mu}^dag + x_n (1 + gamma_mu) lam_{n+mu}^dag ],
+ * the complex derivative dL/dRe U + i dL/dIm U. With project = 1 the output is instead the
+ * su(3)-valued force F = (i/2) TA(U G^dag), TA(Y) = (Y - Y^dag)/2 - tr(Y - Y^dag)/6, for which
+ * dL/de_a = 2 tr(T_a F) under U -> exp(i e_a T_a) U. x, lam: device [V][3][4]; dU: device
+ * [4][V][3][3] complex128. Asynchronous.
+ */
+wd_status wd_gauge_grad(wd_gauge* g, const double* x, const double* lam, double* dU, int project,
+                        void* stream);
+
+/* Human-readable name of a status code (static string). */
+const char* wd_status_str(wd_status s);
+/* Copy the calling thread's last error message into buf (n bytes, NUL-terminated). */
+wd_status wd_last_error(char* buf, size_t n);
+
+/*
+ * Kernel timing (measurement support, not part of the method). When enabled, the library
+ * brackets each launch of the named kernel classes with HIP events on the launch stream and
+ * accumulates their durations; reading the totals synchronises the recorded events.
+ * class: 0 = low-precision even-odd hop, 1 = FP64 hop, 2 = fused vector sweeps.
+ */
+void wd_timing_enable(int on);
+void wd_timing_reset(void);
+wd_status wd_timing_get(int kernel_class, double* total_ms, long* launches, double* bytes);
+
+/* Bytes of device memory held by a handle (links and cached workspaces). */
+size_t wd_gauge_device_bytes(const wd_gauge* g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WDIRAC_H */

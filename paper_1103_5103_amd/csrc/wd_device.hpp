@@ -1,0 +1,301 @@
+// Device-side building blocks of libwdirac: storage formats, complex arithmetic, spinor and
+// link loads/stores, lattice geometry and deterministic block reductions.
+//
+// Internal layout (structure of arrays, site index innermost, as the paper argues in Sec. 3-4
+// for coalesced access; the chunking is our own, chosen so that each lane issues 8- or 16-byte
+// loads on gfx950):
+//   * a "half field" holds the sites of one parity in checkerboard order
+//       cb = (x >> 1) + (X/2) * (y + Y * (z + Z * t));
+//     even sites first, then odd ones, as in the even-first site map of Sec. 4;
+//   * a spinor of 12 complex numbers (colour c, spin s, index c*4 + s) is split into chunks:
+//       F64: 12 x double2 (one complex each)  F32: 6 x float4 (two complex each)
+//       F16: 3 x half8 (four complex each) plus one float per site holding the largest
+//            |component|, by which the stored values are divided;
+//     chunk j of site i lives at base[j * cs + i] (cs = chunk stride in sites);
+//   * links are stored per output parity and per output site: 8 matrices per site, slots 0..3
+//     the forward links U_mu(n), slots 4..7 the backward links already daggered,
+//     U_mu(n - mu)^dag, so every hop reads its 8 links fully coalesced. 12-real formats keep rows
+//     0 and 1 and rebuild row 2 = conj(row0 x row1), exact for SU(3).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wd {
+
+// ---------------------------------------------------------------- formats
+enum SpinorFmt { SF64 = 0, SF32 = 1, SF16 = 2 };
+enum LinkFmt { L64_18 = 0, L64_12 = 1, L32_12 = 2, L16_12 = 3, LB16_12 = 4, L32_18 = 5, NLINKFMT = 6 };
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ constexpr int spinor_chunks(int f) { return f == SF64 ? 12 : (f == SF32 ? 6 : 3); }
+__host__ __device__ constexpr int spinor_chunk_bytes(int f) { return 16; }
+__host__ __device__ constexpr int link_chunks(int f)
+{
+    return f == L64_18 ? 9 : f == L64_12 ? 6 : f == L32_18 ? 0 : 3;
+}
+__host__ __device__ constexpr int link_chunk_bytes(int f)
+{
+    return (f == L64_18 || f == L64_12 || f == L32_12) ? 16 : 8;
+}
+__host__ __device__ constexpr bool link_recon12(int f) { return f != L64_18 && f != L32_18; }
+
+// ---------------------------------------------------------------- complex
+template <class T>
+struct cx {
+    T re, im;
+};
+template <class T> __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <class T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <class T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <class T> __device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <class T> __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <class T> __device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <class T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+// multiply by the unit i^k (k = 0..3), free of arithmetic
+template <int K, class T> __device__ __forceinline__ cx<T> mul_ik(cx<T> a)
+{
+    constexpr int k = ((K % 4) + 4) % 4;
+    if constexpr (k == 0) return a;
+    else if constexpr (k == 1) return {-a.im, a.re};
+    else if constexpr (k == 2) return {-a.re, -a.im};
+    else return {a.im, -a.re};
+}
+
+// ---------------------------------------------------------------- geometry
+struct Geo {
+    int X, Y, Z, T;
+    int Xh;     // X / 2
+    int Vh;     // sites per parity
+    int stride; // sites per parity rounded up to the block size (allocation unit)
+    int anti;   // antiperiodic in t
+};
+
+// site coordinates of checkerboard index cb of parity p
+__device__ __forceinline__ void cb_coords(const Geo& g, int p, int cb, int& x, int& y, int& z, int& t)
+{
+    unsigned u = (unsigned)cb;
+    const unsigned xh = u % (unsigned)g.Xh;
+    u /= (unsigned)g.Xh;
+    y = (int)(u % (unsigned)g.Y);
+    u /= (unsigned)g.Y;
+    z = (int)(u % (unsigned)g.Z);
+    t = (int)(u / (unsigned)g.Z);
+    x = 2 * (int)xh + ((p + y + z + t) & 1);
+}
+__device__ __forceinline__ int cb_index(const Geo& g, int x, int y, int z, int t)
+{
+    return (x >> 1) + g.Xh * (y + g.Y * (z + g.Z * t));
+}
+
+// ---------------------------------------------------------------- field views
+struct SpinorRef {
+    void* p;     // chunk 0 of site 0 of this view
+    float* nrm;  // F16 only: per-site scale
+    long cs;     // chunk stride in sites
+};
+
+template <int SF> struct SReal { using T = float; };
+template <> struct SReal<SF64> { using T = double; };
+
+template <int SF, class T>
+__device__ __forceinline__ void load_spinor(const SpinorRef& r, long i, cx<T> v[12])
+{
+    if constexpr (SF == SF64) {
+        const double2* p = (const double2*)r.p;
+#pragma unroll
+        for (int j = 0; j < 12; j++) {
+            double2 q = p[j * r.cs + i];
+            v[j] = mk<T>((T)q.x, (T)q.y);
+        }
+    } else if constexpr (SF == SF32) {
+        const float4* p = (const float4*)r.p;
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            float4 q = p[j * r.cs + i];
+            v[2 * j] = mk<T>((T)q.x, (T)q.y);
+            v[2 * j + 1] = mk<T>((T)q.z, (T)q.w);
+        }
+    } else {
+        const h8* p = (const h8*)r.p;
+        const float n = r.nrm[i];
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            h8 q = p[j * r.cs + i];
+#pragma unroll
+            for (int k = 0; k < 4; k++) v[4 * j + k] = mk<T>((T)((float)q[2 * k] * n), (T)((float)q[2 * k + 1] * n));
+        }
+    }
+}
+
+template <int SF, class T>
+__device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const cx<T> v[12])
+{
+    if constexpr (SF == SF64) {
+        double2* p = (double2*)r.p;
+#pragma unroll
+        for (int j = 0; j < 12; j++) p[j * r.cs + i] = make_double2((double)v[j].re, (double)v[j].im);
+    } else if constexpr (SF == SF32) {
+        float4* p = (float4*)r.p;
+#pragma unroll
+        for (int j = 0; j < 6; j++)
+            p[j * r.cs + i] = make_float4((float)v[2 * j].re, (float)v[2 * j].im, (float)v[2 * j + 1].re,
+                                          (float)v[2 * j + 1].im);
+    } else {
+        h8* p = (h8*)r.p;
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf((float)v[k].re), fabsf((float)v[k].im)));
+        const float inv = m > 0.f ? 1.0f / m : 0.f;
+        r.nrm[i] = m;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            h8 q;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                q[2 * k] = (_Float16)((float)v[4 * j + k].re * inv);
+                q[2 * k + 1] = (_Float16)((float)v[4 * j + k].im * inv);
+            }
+            p[j * r.cs + i] = q;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- links
+__device__ __forceinline__ float bf16_to_f32(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
+// round to nearest even; inputs are finite link entries
+__device__ __forceinline__ unsigned short f32_to_bf16(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+// Load link slot k of output site i into W[3][3]. base: link array of this output parity,
+// chunk j of slot k at base[(k * nchunks + j) * lcs + i].
+template <int LF, class T>
+__device__ __forceinline__ void load_link(const void* base, long lcs, int k, long i, cx<T> W[9])
+{
+    if constexpr (LF == L64_18 || LF == L64_12) {
+        constexpr int nc = link_chunks(LF);
+        const double2* p = (const double2*)base + (long)k * nc * lcs + i;
+#pragma unroll
+        for (int j = 0; j < nc; j++) {
+            double2 q = p[j * lcs];
+            W[j] = mk<T>((T)q.x, (T)q.y);
+        }
+    } else if constexpr (LF == L32_12) {
+        const float4* p = (const float4*)base + (long)k * 3 * lcs + i;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            float4 q = p[j * lcs];
+            W[2 * j] = mk<T>((T)q.x, (T)q.y);
+            W[2 * j + 1] = mk<T>((T)q.z, (T)q.w);
+        }
+    } else if constexpr (LF == L16_12) {
+        const h4* p = (const h4*)base + (long)k * 3 * lcs + i;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            h4 q = p[j * lcs];
+            W[2 * j] = mk<T>((T)(float)q[0], (T)(float)q[1]);
+            W[2 * j + 1] = mk<T>((T)(float)q[2], (T)(float)q[3]);
+        }
+    } else if constexpr (LF == LB16_12) {
+        const u16x4* p = (const u16x4*)base + (long)k * 3 * lcs + i;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            u16x4 q = p[j * lcs];
+            W[2 * j] = mk<T>((T)bf16_to_f32(q[0]), (T)bf16_to_f32(q[1]));
+            W[2 * j + 1] = mk<T>((T)bf16_to_f32(q[2]), (T)bf16_to_f32(q[3]));
+        }
+    }
+    if constexpr (link_recon12(LF)) {
+        // row 2 = conj(row0 x row1)
+        W[6] = cconj(W[1] * W[5] - W[2] * W[4]);
+        W[7] = cconj(W[2] * W[3] - W[0] * W[5]);
+        W[8] = cconj(W[0] * W[4] - W[1] * W[3]);
+    }
+}
+
+template <int LF>
+__device__ __forceinline__ void store_link(void* base, long lcs, int k, long i, const cx<double> W[9])
+{
+    if constexpr (LF == L64_18 || LF == L64_12) {
+        constexpr int nc = link_chunks(LF);
+        double2* p = (double2*)base + (long)k * nc * lcs + i;
+#pragma unroll
+        for (int j = 0; j < nc; j++) p[j * lcs] = make_double2(W[j].re, W[j].im);
+    } else if constexpr (LF == L32_12) {
+        float4* p = (float4*)base + (long)k * 3 * lcs + i;
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            p[j * lcs] = make_float4((float)W[2 * j].re, (float)W[2 * j].im, (float)W[2 * j + 1].re,
+                                     (float)W[2 * j + 1].im);
+    } else if constexpr (LF == L16_12) {
+        h4* p = (h4*)base + (long)k * 3 * lcs + i;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            h4 q;
+            q[0] = (_Float16)(float)W[2 * j].re;
+            q[1] = (_Float16)(float)W[2 * j].im;
+            q[2] = (_Float16)(float)W[2 * j + 1].re;
+            q[3] = (_Float16)(float)W[2 * j + 1].im;
+            p[j * lcs] = q;
+        }
+    } else if constexpr (LF == LB16_12) {
+        u16x4* p = (u16x4*)base + (long)k * 3 * lcs + i;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            u16x4 q;
+            q[0] = f32_to_bf16((float)W[2 * j].re);
+            q[1] = f32_to_bf16((float)W[2 * j].im);
+            q[2] = f32_to_bf16((float)W[2 * j + 1].re);
+            q[3] = f32_to_bf16((float)W[2 * j + 1].im);
+            p[j * lcs] = q;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- reductions
+constexpr int BLOCK = 256;
+constexpr int NRED = 4;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum NR values over the block in a fixed order; result valid in thread 0.
+template <int NR>
+__device__ __forceinline__ void block_sum(double v[NR], double* lds /* [NR][BLOCK/64] */)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NR; k++) {
+        double s = wave_sum(v[k]);
+        if (lane == 0) lds[k * (BLOCK / 64) + wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NR; k++) {
+            double s = 0;
+            for (int w = 0; w < BLOCK / 64; w++) s += lds[k * (BLOCK / 64) + w];
+            v[k] = s;
+        }
+    }
+}
+
+} // namespace wd

@@ -1,0 +1,127 @@
+// Host-side internals of libwdirac: the gauge handle, workspace fields, job tables and the
+// error/timing plumbing shared by the solver drivers and the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/wdirac.h"
+#include "wd_kernels.hpp"
+
+namespace wd {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    wd_status code;
+    std::string msg;
+};
+void set_error(const std::string& msg);
+#define WD_CHECK_HIP(call)                                                                                       \
+    do {                                                                                                         \
+        hipError_t e_ = (call);                                                                                  \
+        if (e_ != hipSuccess)                                                                                    \
+            throw ::wd::Error{WD_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)};                    \
+    } while (0)
+#define WD_REQUIRE(cond, msg)                                                                                    \
+    do {                                                                                                         \
+        if (!(cond)) throw ::wd::Error{WD_ERR_ARG, msg};                                                         \
+    } while (0)
+
+// ---------------------------------------------------------------- device memory
+struct DevMem {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    explicit DevMem(size_t n);
+    ~DevMem();
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+};
+
+// An internal spinor field: one half (one parity) or a full field (both halves).
+struct Field {
+    std::shared_ptr<DevMem> mem;
+    int sf = SF64;
+    int halves = 1;
+    long stride = 0;  // sites per half
+    char* base() const { return (char*)mem->p; }
+    float* nrm() const { return sf == SF16 ? (float*)(base() + (size_t)16 * spinor_chunks(sf) * halves * stride) : nullptr; }
+    long cs() const { return stride * halves; }
+    // view of parity p (a full field) or of the single half
+    SpinorRef half(int p) const
+    {
+        SpinorRef r;
+        r.p = base() + (size_t)p * stride * 16;
+        float* n = nrm();
+        r.nrm = n ? n + (size_t)p * stride : nullptr;
+        r.cs = cs();
+        return r;
+    }
+    SpinorRef all() const { return SpinorRef{base(), nrm(), cs()}; }
+    long nsites() const { return stride * halves; }
+};
+size_t field_bytes(int sf, int halves, long stride);
+
+// ---------------------------------------------------------------- timing
+enum { TK_HOP_LO = 0, TK_HOP_F64 = 1, TK_SWEEP = 2, NTK = 3 };
+struct Timer {
+    bool on = false;
+    struct Rec { int cls; hipEvent_t a, b; double bytes; };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[NTK] = {0, 0, 0};
+    double bytes[NTK] = {0, 0, 0};
+    long launches[NTK] = {0, 0, 0};
+    hipEvent_t get();
+    void flush();
+};
+Timer& timer();
+
+// ---------------------------------------------------------------- job tables
+template <class J>
+struct JobTable {
+    std::vector<J> host;
+    std::shared_ptr<DevMem> dev;
+    long nblocks = 0;
+    void upload(hipStream_t s);
+    int n() const { return (int)host.size(); }
+    const J* d() const { return (const J*)dev->p; }
+};
+
+// ---------------------------------------------------------------- gauge handle
+} // namespace wd
+
+struct wd_gauge {
+    wd::Geo geo;
+    long V = 0;
+    std::unique_ptr<wd::DevMem> links[wd::NLINKFMT];  // both output parities, [parity][8][chunks][stride]
+    std::map<std::string, wd::Field> ws;              // cached workspace fields
+    std::map<std::string, std::shared_ptr<wd::DevMem>> raw;
+    std::map<std::string, wd::JobTable<wd::HopJob>> hop_tables;
+    hipStream_t stream = nullptr;
+    const void* lk(int lf, int parity) const;
+    long lcs() const { return geo.stride; }
+    wd::Field& field(const std::string& key, int sf, int halves);
+    void* rawbuf(const std::string& key, size_t bytes);
+    void ensure_links(int lf, hipStream_t s);
+    size_t device_bytes() const;
+};
+
+namespace wd {
+
+// pinned staging for small host<->device copies
+void* pinned(size_t bytes);
+
+// launch helpers with optional timing
+void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>& t, SysState* sys, int gated,
+             hipStream_t s, double bytes_per_site_total);
+void run_sweep(int op, int sfl, const JobTable<SweepJob>& t, SysState* sys, int gated, hipStream_t s,
+               double bytes_total);
+
+int spinor_fmt_of(wd_prec p);
+int link_fmt_of(wd_prec p, int recon);
+
+} // namespace wd

@@ -1,0 +1,818 @@
+// Kernels of libwdirac for gfx950 (CDNA4, wave64).
+//
+//  * k_hop     : the Wilson hopping term between parities (Sec. 2, eq. 3-4; the paper's dslash,
+//                Alg. 1) with the spin-projection trick of Table 1 and a fused epilogue
+//                out = c0 x0 + c1 x1 + c2 * hop, optionally followed by FP64 reductions and a
+//                finisher that updates the BiCGstab scalars.
+//  * k_sweep   : the fused BiCGstab vector updates of one iteration (Sec. 5: the x <- x - beta s +
+//                chi w update and its companions), plus the BiCGstab-M shift sweep (Sec. 6.1).
+//  * packing   : canonical complex128 layout <-> internal checkerboarded structure of arrays.
+//  * k_grad    : link derivative of Re<eta, M^{-1} b> (outer products of projected spinors).
+#include "wd_kernels.hpp"
+
+namespace wd {
+
+// ================================================================ finishers
+
+__device__ __forceinline__ double2 c_div(double2 a, double2 b)
+{
+    double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double2 c_mul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 c_add(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 c_neg(double2 a) { return make_double2(-a.x, -a.y); }
+__device__ __forceinline__ double2 c_real(double r) { return make_double2(r, 0.0); }
+__device__ __forceinline__ double c_abs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ bool c_finite(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+
+template <int FIN>
+__device__ void finish(SysState* S, const double* tot)
+{
+    for (int k = 0; k < NRED; k++) S->red[k] = tot[k];
+    if constexpr (FIN == FIN_BETA) {
+        const double2 rhAs = make_double2(tot[0], tot[1]);
+        if (!c_finite(rhAs)) { S->status = ST_NAN; return; }
+        if (c_abs2(rhAs) == 0.0) { S->status = ST_BREAKDOWN; return; }
+        const double2 beta = c_neg(c_div(S->delta, rhAs));
+        S->beta = beta;
+        // shifted systems: zeta_{n+1} and beta^sigma_n from the collinearity of the residuals
+        for (int i = 0; i < S->nshift; i++) {
+            ShiftScal& q = S->sh[i];
+            if (!q.active) continue;
+            // den = beta alpha (zeta_prev - zeta) + zeta_prev beta_prev (1 - sigma beta)
+            double2 den = c_add(c_mul(c_mul(beta, S->alpha), c_sub(q.zeta_prev, q.zeta)),
+                                c_mul(c_mul(q.zeta_prev, S->beta_prev),
+                                      c_sub(c_real(1.0), c_mul(c_real(q.sigma), beta))));
+            q.zeta_next = c_div(c_mul(c_mul(q.zeta, q.zeta_prev), S->beta_prev), den);
+            q.beta_s = c_div(c_mul(beta, q.zeta_next), q.zeta);
+        }
+    } else if constexpr (FIN == FIN_CHI) {
+        const double2 aww = make_double2(tot[0], tot[1]);
+        const double awaw = tot[2];
+        if (!c_finite(aww) || !isfinite(awaw)) { S->status = ST_NAN; return; }
+        if (awaw == 0.0) { S->status = ST_BREAKDOWN; return; }
+        const double2 chi = make_double2(aww.x / awaw, aww.y / awaw);
+        S->chi = chi;
+        for (int i = 0; i < S->nshift; i++) {
+            ShiftScal& q = S->sh[i];
+            if (!q.active) continue;
+            double2 d = c_add(c_real(1.0), c_mul(chi, c_real(q.sigma)));
+            q.chi_s = c_div(chi, d);
+            q.rho_next = c_div(q.rho, d);
+        }
+    } else if constexpr (FIN == FIN_ALPHA) {
+        const double2 d1 = make_double2(tot[0], tot[1]);
+        const double rr = tot[2];
+        S->iter += 1;
+        S->rr = rr;
+        const double2 alpha = c_neg(c_div(c_mul(S->beta, d1), c_mul(S->delta, S->chi)));
+        int pend = ST_RUNNING;
+        if (!isfinite(rr) || !c_finite(d1)) pend = ST_NAN;
+        else if (rr <= S->target2) pend = ST_CONVERGED;
+        else if (S->mixed && rr < S->delta_rel2 * S->maxrr) pend = ST_RELIABLE;
+        else if (S->iter >= S->maxit) pend = ST_MAXIT;
+        else if (c_abs2(d1) == 0.0) pend = ST_BREAKDOWN;
+        S->pending = pend;
+        if (rr > S->maxrr) S->maxrr = rr;
+        for (int i = 0; i < S->nshift; i++) {
+            ShiftScal& q = S->sh[i];
+            if (!q.active) continue;
+            // alpha^sigma_{n+1} = alpha_{n+1} zeta_{n+1} beta^sigma_n / (zeta_n beta_n)
+            q.alpha_s = c_div(c_mul(c_mul(alpha, q.zeta_next), q.beta_s), c_mul(q.zeta, S->beta));
+            double2 zr = c_mul(q.zeta_next, q.rho_next);
+            if (c_abs2(zr) * rr < S->shift_target2) q.freeze = 1;
+        }
+        S->alpha = alpha;
+        S->delta = d1;
+    } else if constexpr (FIN == FIN_END) {
+        S->status = S->pending;
+        S->beta_prev = S->beta;
+        for (int i = 0; i < S->nshift; i++) {
+            ShiftScal& q = S->sh[i];
+            if (!q.active) continue;
+            q.zeta_prev = q.zeta;
+            q.zeta = q.zeta_next;
+            q.rho = q.rho_next;
+            if (q.freeze) { q.active = 0; q.conv_iter = S->iter; }
+        }
+        if (S->nshift > 0) S->rsel ^= 1;
+    } else if constexpr (FIN == FIN_RESTART) {
+        S->delta = make_double2(tot[0], tot[1]);
+        S->rr = tot[2];
+        S->maxrr = tot[2];
+        S->status = (isfinite(tot[2]) && c_finite(S->delta)) ? ST_RUNNING : ST_NAN;
+        S->pending = S->status;
+    }
+}
+
+// Block reduction of NR partial sums, ticket, and (in the last block of the system's
+// reduction group) a fixed-order final sum followed by the finisher.
+template <int NR, int FIN>
+__device__ __forceinline__ void reduce_finish(double v[NRED], SysState* S, int rb, int rnb)
+{
+    __shared__ double lds[NRED * (BLOCK / 64)];
+    __shared__ int amlast;
+    if constexpr (NR > 0) block_sum<NR>(v, lds);
+    if (threadIdx.x == 0) {
+        if constexpr (NR > 0) {
+#pragma unroll
+            for (int k = 0; k < NR; k++) S->partials[(long)rb * NRED + k] = v[k];
+        }
+        __threadfence();
+        unsigned t = atomicAdd(&S->counter, 1u);
+        amlast = (t == (unsigned)(rnb - 1));
+    }
+    __syncthreads();
+    if (!amlast) return;
+    __threadfence();
+    double tot[NRED] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (NR > 0) {
+        double acc[NRED] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = threadIdx.x; i < rnb; i += BLOCK) {
+#pragma unroll
+            for (int k = 0; k < NR; k++) acc[k] += __builtin_nontemporal_load(&S->partials[(long)i * NRED + k]);
+        }
+        __syncthreads();
+        block_sum<NR>(acc, lds);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < NR; k++) tot[k] = acc[k];
+    }
+    if (threadIdx.x == 0) {
+        finish<FIN>(S, tot);
+        atomicExch(&S->counter, 0u);
+    }
+}
+
+// job of block b: jobs are sorted by blk0
+template <class J>
+__device__ __forceinline__ int find_job(const J* jobs, int njobs, int b)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].blk0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ================================================================ hop
+
+// Projection data of Table 1: with the hop's spin matrix written P = v1 v1^dag + v2 v2^dag,
+// v1^dag has a 1 in spin slot 3 and the unit e = i^E in slot I1, v2^dag has a 1 in slot 2 and
+// f = i^F in slot I2. For 1 - gamma_mu (forward hop of M):
+//   mu = x: e = i,  f = i   (I1 = 0, I2 = 1)      mu = y: e = -1, f = 1  (I1 = 0, I2 = 1)
+//   mu = z: e = -i, f = i   (I1 = 1, I2 = 0)      mu = t: e = 1,  f = 1  (I1 = 1, I2 = 0)
+// and 1 + gamma_mu negates e and f. Shrink: h1 = psi_3 + conj(e) psi_I1, h2 = psi_2 + conj(f) psi_I2;
+// expand: col3 += g1, col I1 += e g1, col2 += g2, col I2 += f g2 with g = U h (colour multiply).
+template <int MU> struct Proj;
+template <> struct Proj<0> { static constexpr int E = 1, F = 1, I1 = 0, I2 = 1; };
+template <> struct Proj<1> { static constexpr int E = 2, F = 0, I1 = 0, I2 = 1; };
+template <> struct Proj<2> { static constexpr int E = 3, F = 1, I1 = 1, I2 = 0; };
+template <> struct Proj<3> { static constexpr int E = 0, F = 0, I1 = 1, I2 = 0; };
+
+template <int MU, int D, bool DAG, int SFI, int LF, class T>
+__device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int z, int t, const SpinorRef& in,
+                                        const void* links, long lcs, cx<T> acc[12])
+{
+    int xx = x, yy = y, zz = z, tt = t;
+    if constexpr (MU == 0) xx = D == 0 ? (x + 1 == g.X ? 0 : x + 1) : (x == 0 ? g.X - 1 : x - 1);
+    if constexpr (MU == 1) yy = D == 0 ? (y + 1 == g.Y ? 0 : y + 1) : (y == 0 ? g.Y - 1 : y - 1);
+    if constexpr (MU == 2) zz = D == 0 ? (z + 1 == g.Z ? 0 : z + 1) : (z == 0 ? g.Z - 1 : z - 1);
+    if constexpr (MU == 3) tt = D == 0 ? (t + 1 == g.T ? 0 : t + 1) : (t == 0 ? g.T - 1 : t - 1);
+    const int nb = cb_index(g, xx, yy, zz, tt);
+
+    cx<T> psi[12];
+    load_spinor<SFI, T>(in, nb, psi);
+    constexpr bool minus = (D == 0) != DAG;  // projector 1 - gamma
+    constexpr int E = Proj<MU>::E + (minus ? 0 : 2);
+    constexpr int F = Proj<MU>::F + (minus ? 0 : 2);
+    constexpr int I1 = Proj<MU>::I1, I2 = Proj<MU>::I2;
+    cx<T> h1[3], h2[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        h1[c] = psi[c * 4 + 3] + mul_ik<-E>(psi[c * 4 + I1]);
+        h2[c] = psi[c * 4 + 2] + mul_ik<-F>(psi[c * 4 + I2]);
+    }
+    cx<T> W[9];
+    load_link<LF, T>(links, lcs, D == 0 ? MU : 4 + MU, cb, W);
+    cx<T> g1[3], g2[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        g1[a] = W[a * 3] * h1[0] + W[a * 3 + 1] * h1[1] + W[a * 3 + 2] * h1[2];
+        g2[a] = W[a * 3] * h2[0] + W[a * 3 + 1] * h2[1] + W[a * 3 + 2] * h2[2];
+    }
+    if constexpr (MU == 3) {
+        const bool flip = g.anti && (D == 0 ? (t == g.T - 1) : (t == 0));
+        if (flip) {
+#pragma unroll
+            for (int a = 0; a < 3; a++) { g1[a] = -g1[a]; g2[a] = -g2[a]; }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        acc[c * 4 + 3] = acc[c * 4 + 3] + g1[c];
+        acc[c * 4 + 2] = acc[c * 4 + 2] + g2[c];
+        acc[c * 4 + I1] = acc[c * 4 + I1] + mul_ik<E>(g1[c]);
+        acc[c * 4 + I2] = acc[c * 4 + I2] + mul_ik<F>(g2[c]);
+    }
+}
+
+template <bool DAG, int SFI, int LF, class T>
+__device__ __forceinline__ void hop_site(const Geo& g, int p, int cb, const SpinorRef& in, const void* links, long lcs,
+                                         cx<T> acc[12])
+{
+    int x, y, z, t;
+    cb_coords(g, p, cb, x, y, z, t);
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc[k] = mk<T>(T(0), T(0));
+    hop_dir<0, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    hop_dir<0, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    hop_dir<1, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    hop_dir<1, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    hop_dir<2, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    hop_dir<2, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    hop_dir<3, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    hop_dir<3, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+}
+
+template <int SF, int LF, bool DAG, int RED, int FIN>
+__global__ __launch_bounds__(BLOCK) void k_hop(const HopJob* __restrict__ jobs, int njobs, SysState* __restrict__ sys,
+                                               int gated)
+{
+    using T = typename SReal<SF>::T;
+    const int b = blockIdx.x;
+    const HopJob& J = jobs[find_job(jobs, njobs, b)];
+    SysState* S = sys + J.sys;
+    if (gated && S->status != ST_RUNNING) return;
+    const int lb = b - J.blk0;
+    const int cb = lb * BLOCK + threadIdx.x;
+    double v[NRED] = {0.0, 0.0, 0.0, 0.0};
+    if (cb < J.g.Vh) {
+        cx<T> acc[12];
+        hop_site<DAG, SF, LF, T>(J.g, J.parity, cb, J.in, J.links, J.lcs, acc);
+        const T c2 = (T)J.c2;
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[k] = c2 * acc[k];
+        cx<T> x0[12];
+        if (J.x0.p) {
+            load_spinor<SF, T>(J.x0, cb, x0);
+            const T c0 = (T)J.c0;
+#pragma unroll
+            for (int k = 0; k < 12; k++) acc[k] = acc[k] + c0 * x0[k];
+        }
+        if (J.x1.p) {
+            cx<T> x1[12];
+            load_spinor<SF, T>(J.x1, cb, x1);
+            const T c1 = (T)J.c1;
+#pragma unroll
+            for (int k = 0; k < 12; k++) acc[k] = acc[k] + c1 * x1[k];
+        }
+        store_spinor<SF, T>(J.out, cb, acc);
+        if constexpr (RED == RED_ZDOT) {
+            cx<T> z[12];
+            load_spinor<SF, T>(J.z, cb, z);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                v[0] += (double)z[k].re * acc[k].re + (double)z[k].im * acc[k].im;
+                v[1] += (double)z[k].re * acc[k].im - (double)z[k].im * acc[k].re;
+            }
+        } else if constexpr (RED == RED_OUTX) {
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                v[0] += (double)acc[k].re * x0[k].re + (double)acc[k].im * x0[k].im;
+                v[1] += (double)acc[k].re * x0[k].im - (double)acc[k].im * x0[k].re;
+                v[2] += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
+            }
+        } else if constexpr (RED == RED_NORM) {
+#pragma unroll
+            for (int k = 0; k < 12; k++) v[2] += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
+        }
+    }
+    if constexpr (RED != RED_NONE || FIN != FIN_STORE) {
+        constexpr int NR = RED == RED_NONE ? 0 : 3;
+        reduce_finish<NR, FIN>(v, S, J.rblk0 + lb, J.rnblk);
+    }
+}
+
+// ================================================================ sweeps
+
+template <class T> __device__ __forceinline__ cx<T> cvt(double2 a) { return mk<T>((T)a.x, (T)a.y); }
+
+template <int OP, int SFL>
+__global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jobs, int njobs,
+                                                 SysState* __restrict__ sys, int gated)
+{
+    using T = typename SReal<SFL>::T;
+    constexpr int SFX = SFL == SF64 ? SF64 : SF32;  // storage of the low-precision solution
+    const int b = blockIdx.x;
+    const SweepJob& J = jobs[find_job(jobs, njobs, b)];
+    SysState* S = sys + J.sys;
+    if (gated && S->status != ST_RUNNING) return;
+    const int lb = b - J.blk0;
+    const long i = (long)lb * BLOCK + threadIdx.x;
+    const bool ok = i < J.n;
+    double v[NRED] = {0.0, 0.0, 0.0, 0.0};
+    const int rsel = S->rsel;
+    const SpinorRef& Rcur = rsel ? J.f[R_F3] : J.f[R_F1];  // OP_W / OP_S / OP_SHIFT role layout
+    const SpinorRef& Rnxt = rsel ? J.f[R_F1] : J.f[R_F3];
+
+    if constexpr (OP == OP_W) {
+        // w = r + beta A s
+        if (ok) {
+            const cx<T> beta = cvt<T>(S->beta);
+            cx<T> r[12], as[12];
+            load_spinor<SFL, T>(Rcur, i, r);
+            load_spinor<SFL, T>(J.f[R_F2], i, as);
+#pragma unroll
+            for (int k = 0; k < 12; k++) r[k] = r[k] + beta * as[k];
+            store_spinor<SFL, T>(J.f[R_F0], i, r);
+        }
+    } else if constexpr (OP == OP_XR) {
+        // x <- x - beta s + chi w ; r_{n+1} = w - chi A w ; <rhat, r_{n+1}>, |r_{n+1}|^2
+        if (ok) {
+            const cx<T> beta = cvt<T>(S->beta), chi = cvt<T>(S->chi);
+            cx<T> x[12], s[12], w[12];
+            load_spinor<SFX, T>(J.f[R_F0], i, x);
+            load_spinor<SFL, T>(J.f[R_F2], i, s);
+            load_spinor<SFL, T>(J.f[R_F3], i, w);
+#pragma unroll
+            for (int k = 0; k < 12; k++) x[k] = x[k] - beta * s[k] + chi * w[k];
+            store_spinor<SFX, T>(J.f[R_F0], i, x);
+            cx<T> aw[12];
+            load_spinor<SFL, T>(J.f[R_F4], i, aw);
+#pragma unroll
+            for (int k = 0; k < 12; k++) w[k] = w[k] - chi * aw[k];
+            // the new residual goes to the buffer not holding r_n
+            store_spinor<SFL, T>(rsel ? J.f[R_F1] : J.f[R_F6], i, w);
+            cx<T> rh[12];
+            load_spinor<SFL, T>(J.f[R_F5], i, rh);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                v[0] += (double)rh[k].re * w[k].re + (double)rh[k].im * w[k].im;
+                v[1] += (double)rh[k].re * w[k].im - (double)rh[k].im * w[k].re;
+                v[2] += (double)w[k].re * w[k].re + (double)w[k].im * w[k].im;
+            }
+        }
+        reduce_finish<3, FIN_ALPHA>(v, S, J.rblk0 + lb, J.rnblk);
+    } else if constexpr (OP == OP_S) {
+        // s <- r_{n+1} + alpha (s - chi A s)
+        if (ok) {
+            const cx<T> alpha = cvt<T>(S->alpha), chi = cvt<T>(S->chi);
+            cx<T> r[12], s[12], as[12];
+            load_spinor<SFL, T>(Rnxt, i, r);
+            load_spinor<SFL, T>(J.f[R_F0], i, s);
+            load_spinor<SFL, T>(J.f[R_F2], i, as);
+#pragma unroll
+            for (int k = 0; k < 12; k++) s[k] = r[k] + alpha * (s[k] - chi * as[k]);
+            store_spinor<SFL, T>(J.f[R_F0], i, s);
+        }
+        reduce_finish<0, FIN_END>(v, S, J.rblk0 + lb, J.rnblk);
+    } else if constexpr (OP == OP_SHIFT) {
+        // BiCGstab-M: base s update, then every active shifted system
+        //   x^s <- x^s - beta^s s^s + chi^s rho_n zeta_{n+1} w
+        //   s^s <- zeta_{n+1} rho_{n+1} r_{n+1} + alpha^s (s^s - (chi^s/beta^s) rho_n (zeta_{n+1} w - zeta_n r_n))
+        if (ok) {
+            const cx<T> alpha = cvt<T>(S->alpha), chi = cvt<T>(S->chi);
+            cx<T> rn[12], r1[12], w[12], s[12], as[12];
+            load_spinor<SFL, T>(Rcur, i, rn);
+            load_spinor<SFL, T>(Rnxt, i, r1);
+            load_spinor<SFL, T>(J.f[R_F4], i, w);
+            load_spinor<SFL, T>(J.f[R_F0], i, s);
+            load_spinor<SFL, T>(J.f[R_F2], i, as);
+#pragma unroll
+            for (int k = 0; k < 12; k++) s[k] = r1[k] + alpha * (s[k] - chi * as[k]);
+            store_spinor<SFL, T>(J.f[R_F0], i, s);
+            const int ns = S->nshift;
+            for (int q = 0; q < ns; q++) {
+                const ShiftScal& Q = S->sh[q];
+                if (!Q.active) continue;
+                const SpinorRef xr = S->shv[2 * q], sr = S->shv[2 * q + 1];
+                const cx<T> bs = cvt<T>(Q.beta_s);
+                const cx<T> cxw = cvt<T>(c_mul(c_mul(Q.chi_s, Q.rho), Q.zeta_next));
+                const cx<T> zr1 = cvt<T>(c_mul(Q.zeta_next, Q.rho_next));
+                const cx<T> as_ = cvt<T>(Q.alpha_s);
+                const cx<T> cb_ = cvt<T>(c_mul(c_div(Q.chi_s, Q.beta_s), Q.rho));
+                const cx<T> zn1 = cvt<T>(Q.zeta_next), zn = cvt<T>(Q.zeta);
+                cx<T> xs[12], ss[12];
+                load_spinor<SFL, T>(xr, i, xs);
+                load_spinor<SFL, T>(sr, i, ss);
+#pragma unroll
+                for (int k = 0; k < 12; k++) {
+                    xs[k] = xs[k] - bs * ss[k] + cxw * w[k];
+                    ss[k] = zr1 * r1[k] + as_ * (ss[k] - cb_ * (zn1 * w[k] - zn * rn[k]));
+                }
+                store_spinor<SFL, T>(xr, i, xs);
+                store_spinor<SFL, T>(sr, i, ss);
+            }
+        }
+        reduce_finish<0, FIN_END>(v, S, J.rblk0 + lb, J.rnblk);
+    } else if constexpr (OP == OP_INIT) {
+        // r_lo = r_hi; optionally rhat = r_lo, s = r_lo, x_lo = 0; then <rhat, r_lo>, |r_lo|^2
+        if (ok) {
+            cx<T> r[12];
+            {
+                cx<double> rh[12];
+                load_spinor<SF64, double>(J.f[R_F1], i, rh);
+#pragma unroll
+                for (int k = 0; k < 12; k++) r[k] = mk<T>((T)rh[k].re, (T)rh[k].im);
+            }
+            store_spinor<SFL, T>(J.f[R_F0], i, r);
+            // the dot products use the values as stored
+            load_spinor<SFL, T>(J.f[R_F0], i, r);
+            if (J.flags & 1) store_spinor<SFL, T>(J.f[R_F2], i, r);
+            if (J.flags & 2) store_spinor<SFL, T>(J.f[R_F3], i, r);
+            if (J.flags & 4) {
+                cx<T> zero[12];
+#pragma unroll
+                for (int k = 0; k < 12; k++) zero[k] = mk<T>(T(0), T(0));
+                store_spinor<SFX, T>(J.f[R_F4], i, zero);
+            }
+            cx<T> rh[12];
+            if (J.flags & 1) {
+#pragma unroll
+                for (int k = 0; k < 12; k++) rh[k] = r[k];
+            } else {
+                load_spinor<SFL, T>(J.f[R_F2], i, rh);
+            }
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                v[0] += (double)rh[k].re * r[k].re + (double)rh[k].im * r[k].im;
+                v[1] += (double)rh[k].re * r[k].im - (double)rh[k].im * r[k].re;
+                v[2] += (double)r[k].re * r[k].re + (double)r[k].im * r[k].im;
+            }
+        }
+        reduce_finish<3, FIN_RESTART>(v, S, J.rblk0 + lb, J.rnblk);
+    } else if constexpr (OP == OP_ACC) {
+        // x_hi += x_lo  (flags & 1: then x_lo = 0)
+        if (ok) {
+            cx<double> xh[12];
+            cx<T> xl[12];
+            load_spinor<SF64, double>(J.f[R_F0], i, xh);
+            load_spinor<SFX, T>(J.f[R_F1], i, xl);
+#pragma unroll
+            for (int k = 0; k < 12; k++) xh[k] = xh[k] + mk<double>((double)xl[k].re, (double)xl[k].im);
+            store_spinor<SF64, double>(J.f[R_F0], i, xh);
+            if (J.flags & 1) {
+#pragma unroll
+                for (int k = 0; k < 12; k++) xl[k] = mk<T>(T(0), T(0));
+                store_spinor<SFX, T>(J.f[R_F1], i, xl);
+            }
+        }
+    } else if constexpr (OP == OP_NORM) {
+        // |f0|^2 in FP64
+        if (ok) {
+            cx<double> a[12];
+            load_spinor<SF64, double>(J.f[R_F0], i, a);
+#pragma unroll
+            for (int k = 0; k < 12; k++) v[2] += a[k].re * a[k].re + a[k].im * a[k].im;
+        }
+        reduce_finish<3, FIN_STORE>(v, S, J.rblk0 + lb, J.rnblk);
+    } else if constexpr (OP == OP_MSINIT) {
+        // BiCGstab-M start: r = s = rhat = b, x = 0, x^sigma = 0, s^sigma = b; |b|^2
+        if (ok) {
+            cx<T> bb[12], zero[12];
+            load_spinor<SFL, T>(J.f[R_F1], i, bb);
+#pragma unroll
+            for (int k = 0; k < 12; k++) zero[k] = mk<T>(T(0), T(0));
+            store_spinor<SFL, T>(J.f[R_F0], i, bb);
+            store_spinor<SFL, T>(J.f[R_F2], i, bb);
+            store_spinor<SFL, T>(J.f[R_F3], i, bb);
+            store_spinor<SFL, T>(J.f[R_F4], i, zero);
+            for (int q = 0; q < S->nshift; q++) {
+                store_spinor<SFL, T>(S->shv[2 * q], i, zero);
+                store_spinor<SFL, T>(S->shv[2 * q + 1], i, bb);
+            }
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                double n2 = (double)bb[k].re * bb[k].re + (double)bb[k].im * bb[k].im;
+                v[0] += n2;
+                v[2] += n2;
+            }
+        }
+        reduce_finish<3, FIN_RESTART>(v, S, J.rblk0 + lb, J.rnblk);
+    }
+}
+
+// ================================================================ packing
+
+// canonical [V][3][4] complex128 (lexicographic) <-> internal per-parity half fields.
+// gamma5 != 0 multiplies spin components 2 and 3 by -1 on the way (gamma5 = diag(1,1,-1,-1)).
+template <int SF>
+__global__ __launch_bounds__(BLOCK) void k_pack_spinor(const double2* __restrict__ src, Geo g, SpinorRef even,
+                                                       SpinorRef odd, int gamma5, double scale)
+{
+    const int p = blockIdx.y;
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    if (cb >= g.Vh) return;
+    int x, y, z, t;
+    cb_coords(g, p, cb, x, y, z, t);
+    const long n = x + (long)g.X * (y + (long)g.Y * (z + (long)g.Z * t));
+    cx<double> v[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        double2 q = src[n * 12 + k];
+        double sg = (gamma5 && (k & 3) >= 2) ? -scale : scale;
+        v[k] = mk<double>(sg * q.x, sg * q.y);
+    }
+    store_spinor<SF, double>(p ? odd : even, cb, v);
+}
+
+template <int SF>
+__global__ __launch_bounds__(BLOCK) void k_unpack_spinor(double2* __restrict__ dst, Geo g, SpinorRef even,
+                                                         SpinorRef odd, int gamma5, double scale)
+{
+    const int p = blockIdx.y;
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    if (cb >= g.Vh) return;
+    int x, y, z, t;
+    cb_coords(g, p, cb, x, y, z, t);
+    const long n = x + (long)g.X * (y + (long)g.Y * (z + (long)g.Z * t));
+    using T = typename SReal<SF>::T;
+    cx<T> v[12];
+    load_spinor<SF, T>(p ? odd : even, cb, v);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        double sg = (gamma5 && (k & 3) >= 2) ? -scale : scale;
+        dst[n * 12 + k] = make_double2(sg * (double)v[k].re, sg * (double)v[k].im);
+    }
+}
+
+// canonical U[4][V][3][3] -> internal FP64 18-real links, 8 slots per output site
+__global__ __launch_bounds__(BLOCK) void k_pack_links(const double2* __restrict__ U, Geo g, void* even, void* odd,
+                                                      long lcs)
+{
+    const int p = blockIdx.y;
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    if (cb >= g.Vh) return;
+    int x, y, z, t;
+    cb_coords(g, p, cb, x, y, z, t);
+    const long V = (long)g.X * g.Y * g.Z * g.T;
+    const long n = x + (long)g.X * (y + (long)g.Y * (z + (long)g.Z * t));
+    void* dst = p ? odd : even;
+    for (int mu = 0; mu < 4; mu++) {
+        cx<double> W[9];
+        const double2* u = U + ((long)mu * V + n) * 9;
+#pragma unroll
+        for (int k = 0; k < 9; k++) W[k] = mk<double>(u[k].x, u[k].y);
+        store_link<L64_18>(dst, lcs, mu, cb, W);
+        int c[4] = {x, y, z, t};
+        const int L[4] = {g.X, g.Y, g.Z, g.T};
+        c[mu] = c[mu] == 0 ? L[mu] - 1 : c[mu] - 1;
+        const long m = c[0] + (long)g.X * (c[1] + (long)g.Y * (c[2] + (long)g.Z * c[3]));
+        const double2* ub = U + ((long)mu * V + m) * 9;
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int bb = 0; bb < 3; bb++) W[a * 3 + bb] = mk<double>(ub[bb * 3 + a].x, -ub[bb * 3 + a].y);
+        store_link<L64_18>(dst, lcs, 4 + mu, cb, W);
+    }
+}
+
+// internal FP64 18-real links -> another link format (same slot layout)
+template <int LF>
+__global__ __launch_bounds__(BLOCK) void k_convert_links(const void* __restrict__ src, void* __restrict__ dst, int Vh,
+                                                         long lcs)
+{
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    const int k = blockIdx.y;
+    if (cb >= Vh) return;
+    cx<double> W[9];
+    load_link<L64_18, double>(src, lcs, k, cb, W);
+    store_link<LF>(dst, lcs, k, cb, W);
+}
+
+// out = sum_j c_j in_j over n complex numbers (FP64, any layout)
+__global__ __launch_bounds__(BLOCK) void k_lincomb(double2* __restrict__ out, const double2* const* __restrict__ ins,
+                                                   const double* __restrict__ c, int k, long n)
+{
+    const long i = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= n) return;
+    double2 s = make_double2(0.0, 0.0);
+    for (int j = 0; j < k; j++) {
+        double2 a = ins[j][i];
+        s.x += c[j] * a.x;
+        s.y += c[j] * a.y;
+    }
+    out[i] = s;
+}
+
+// ================================================================ link gradient
+
+// G_mu(n) = 1/2 s [ lam_n (1 - gamma_mu) x_{n+mu}^dag + x_n (1 + gamma_mu) lam_{n+mu}^dag ]
+// With 1 -/+ gamma = v1 v1^dag + v2 v2^dag (Table 1) each term is a sum of two colour outer
+// products of projected vectors: psi P phi^dag = (psi v1)(phi v1)^dag + (psi v2)(phi v2)^dag.
+template <int MU, bool MINUS>
+__device__ __forceinline__ void proj2(const cx<double> psi[12], cx<double> h1[3], cx<double> h2[3])
+{
+    constexpr int E = Proj<MU>::E + (MINUS ? 0 : 2);
+    constexpr int F = Proj<MU>::F + (MINUS ? 0 : 2);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        h1[c] = psi[c * 4 + 3] + mul_ik<-E>(psi[c * 4 + Proj<MU>::I1]);
+        h2[c] = psi[c * 4 + 2] + mul_ik<-F>(psi[c * 4 + Proj<MU>::I2]);
+    }
+}
+
+template <int MU>
+__device__ __forceinline__ void grad_mu(const Geo& g, long n, int x, int y, int z, int t, const double2* xs,
+                                        const double2* lam, const cx<double> xn[12], const cx<double> ln[12],
+                                        cx<double> G[9])
+{
+    int c[4] = {x, y, z, t};
+    const int L[4] = {g.X, g.Y, g.Z, g.T};
+    c[MU] = c[MU] + 1 == L[MU] ? 0 : c[MU] + 1;
+    const long m = c[0] + (long)g.X * (c[1] + (long)g.Y * (c[2] + (long)g.Z * c[3]));
+    cx<double> xm[12], lm[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        xm[k] = mk<double>(xs[m * 12 + k].x, xs[m * 12 + k].y);
+        lm[k] = mk<double>(lam[m * 12 + k].x, lam[m * 12 + k].y);
+    }
+    cx<double> a1[3], a2[3], b1[3], b2[3], c1[3], c2[3], d1[3], d2[3];
+    proj2<MU, true>(ln, a1, a2);   // lam_n  with 1 - gamma
+    proj2<MU, true>(xm, b1, b2);   // x_{n+mu} with 1 - gamma
+    proj2<MU, false>(xn, c1, c2);  // x_n   with 1 + gamma
+    proj2<MU, false>(lm, d1, d2);  // lam_{n+mu} with 1 + gamma
+    const double s = (MU == 3 && g.anti && t == g.T - 1) ? -0.5 : 0.5;  // 1/2 times the boundary sign
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int bb = 0; bb < 3; bb++) {
+            cx<double> v = cmulc(b1[bb], a1[a]) + cmulc(b2[bb], a2[a]) + cmulc(d1[bb], c1[a]) + cmulc(d2[bb], c2[a]);
+            G[a * 3 + bb] = s * v;
+        }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_grad(const double2* __restrict__ xs, const double2* __restrict__ lam, Geo g,
+                                                const void* __restrict__ lk_even, const void* __restrict__ lk_odd,
+                                                long lcs, double2* __restrict__ out, int project)
+{
+    const long V = (long)g.X * g.Y * g.Z * g.T;
+    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= V) return;
+    int x = (int)(n % g.X);
+    long r = n / g.X;
+    int y = (int)(r % g.Y);
+    r /= g.Y;
+    int z = (int)(r % g.Z);
+    int t = (int)(r / g.Z);
+    cx<double> xn[12], ln[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        xn[k] = mk<double>(xs[n * 12 + k].x, xs[n * 12 + k].y);
+        ln[k] = mk<double>(lam[n * 12 + k].x, lam[n * 12 + k].y);
+    }
+    const int p = (x + y + z + t) & 1;
+    const int cb = cb_index(g, x, y, z, t);
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+        cx<double> G[9];
+        if (mu == 0) grad_mu<0>(g, n, x, y, z, t, xs, lam, xn, ln, G);
+        if (mu == 1) grad_mu<1>(g, n, x, y, z, t, xs, lam, xn, ln, G);
+        if (mu == 2) grad_mu<2>(g, n, x, y, z, t, xs, lam, xn, ln, G);
+        if (mu == 3) grad_mu<3>(g, n, x, y, z, t, xs, lam, xn, ln, G);
+        if (project) {
+            // F = (i/2) TA(U G^dag),  TA(Y) = (Y - Y^dag)/2 - tr(Y - Y^dag)/6
+            cx<double> U[9], Y[9];
+            load_link<L64_18, double>(p ? lk_odd : lk_even, lcs, mu, cb, U);
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+#pragma unroll
+                for (int bb = 0; bb < 3; bb++)
+                    Y[a * 3 + bb] = cmulc(G[bb * 3], U[a * 3]) + cmulc(G[bb * 3 + 1], U[a * 3 + 1]) +
+                                    cmulc(G[bb * 3 + 2], U[a * 3 + 2]);
+            cx<double> A[9];
+#pragma unroll
+            for (int a = 0; a < 3; a++)
+#pragma unroll
+                for (int bb = 0; bb < 3; bb++) A[a * 3 + bb] = 0.5 * (Y[a * 3 + bb] - cconj(Y[bb * 3 + a]));
+            cx<double> tr = (1.0 / 3.0) * (A[0] + A[4] + A[8]);
+            A[0] = A[0] - tr;
+            A[4] = A[4] - tr;
+            A[8] = A[8] - tr;
+#pragma unroll
+            for (int k = 0; k < 9; k++) G[k] = mk<double>(-0.5 * A[k].im, 0.5 * A[k].re);
+        }
+#pragma unroll
+        for (int k = 0; k < 9; k++) out[((long)mu * V + n) * 9 + k] = make_double2(G[k].re, G[k].im);
+    }
+}
+
+// ================================================================ host launchers
+
+static inline dim3 grid1(long nblk) { return dim3((unsigned)nblk); }
+
+#define HOP_CASE(SF_, LF_, DAG_, RED_, FIN_)                                                                        \
+    if (sf == SF_ && lf == LF_ && dag == DAG_ && red == RED_ && fin == FIN_) {                                     \
+        hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs,    \
+                           sys, gated);                                                                           \
+        return hipGetLastError();                                                                                  \
+    }
+#define HOP_REDS(SF_, LF_, DAG_)                                                                                   \
+    HOP_CASE(SF_, LF_, DAG_, RED_NONE, FIN_STORE)                                                                  \
+    HOP_CASE(SF_, LF_, DAG_, RED_NORM, FIN_STORE)                                                                  \
+    HOP_CASE(SF_, LF_, DAG_, RED_ZDOT, FIN_BETA)                                                                   \
+    HOP_CASE(SF_, LF_, DAG_, RED_OUTX, FIN_CHI)
+
+hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
+                      SysState* sys, int gated, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    HOP_REDS(SF64, L64_18, false)
+    HOP_CASE(SF64, L64_18, true, RED_NONE, FIN_STORE)
+    HOP_REDS(SF64, L64_12, false)
+    HOP_REDS(SF32, L32_12, false)
+    HOP_REDS(SF32, L16_12, false)
+    HOP_REDS(SF32, LB16_12, false)
+    HOP_REDS(SF16, L32_12, false)
+    HOP_REDS(SF16, L16_12, false)
+    HOP_REDS(SF16, LB16_12, false)
+    return hipErrorInvalidValue;
+}
+
+#define SWEEP_CASE(OP_, SF_)                                                                                       \
+    if (op == OP_ && sfl == SF_) {                                                                                 \
+        hipLaunchKernelGGL((k_sweep<OP_, SF_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs, sys, gated);       \
+        return hipGetLastError();                                                                                  \
+    }
+#define SWEEP_ALL(SF_)                                                                                             \
+    SWEEP_CASE(OP_W, SF_)                                                                                          \
+    SWEEP_CASE(OP_XR, SF_) SWEEP_CASE(OP_S, SF_) SWEEP_CASE(OP_INIT, SF_) SWEEP_CASE(OP_ACC, SF_)
+
+hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long nblocks, SysState* sys, int gated,
+                        hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    SWEEP_ALL(SF64)
+    SWEEP_ALL(SF32)
+    SWEEP_ALL(SF16)
+    SWEEP_CASE(OP_SHIFT, SF64)
+    SWEEP_CASE(OP_NORM, SF64)
+    SWEEP_CASE(OP_MSINIT, SF64)
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pack_spinor(int sf, const double* src, const Geo& g, SpinorRef even, SpinorRef odd, int gamma5,
+                              double scale, hipStream_t s)
+{
+    dim3 grid((unsigned)((g.Vh + BLOCK - 1) / BLOCK), 2);
+    if (sf == SF64) hipLaunchKernelGGL((k_pack_spinor<SF64>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale);
+    else if (sf == SF32) hipLaunchKernelGGL((k_pack_spinor<SF32>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale);
+    else hipLaunchKernelGGL((k_pack_spinor<SF16>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_spinor(int sf, double* dst, const Geo& g, SpinorRef even, SpinorRef odd, int gamma5,
+                                double scale, hipStream_t s)
+{
+    dim3 grid((unsigned)((g.Vh + BLOCK - 1) / BLOCK), 2);
+    if (sf == SF64) hipLaunchKernelGGL((k_unpack_spinor<SF64>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale);
+    else if (sf == SF32) hipLaunchKernelGGL((k_unpack_spinor<SF32>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale);
+    else hipLaunchKernelGGL((k_unpack_spinor<SF16>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_links(const double* U, const Geo& g, void* even, void* odd, long lcs, hipStream_t s)
+{
+    dim3 grid((unsigned)((g.Vh + BLOCK - 1) / BLOCK), 2);
+    hipLaunchKernelGGL(k_pack_links, grid, dim3(BLOCK), 0, s, (const double2*)U, g, even, odd, lcs);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_links(int lf, const void* src, void* dst, int Vh, long lcs, hipStream_t s)
+{
+    dim3 grid((unsigned)((Vh + BLOCK - 1) / BLOCK), 8);
+    switch (lf) {
+    case L64_12: hipLaunchKernelGGL((k_convert_links<L64_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break;
+    case L32_12: hipLaunchKernelGGL((k_convert_links<L32_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break;
+    case L16_12: hipLaunchKernelGGL((k_convert_links<L16_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break;
+    case LB16_12: hipLaunchKernelGGL((k_convert_links<LB16_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lincomb(double* out, const double* const* ins, const double* c, int k, long ncomplex, hipStream_t s)
+{
+    long nb = (ncomplex + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(k_lincomb, grid1(nb), dim3(BLOCK), 0, s, (double2*)out, (const double2* const*)ins, c, k,
+                       ncomplex);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(const double* x, const double* lam, const Geo& g, const void* lk_even, const void* lk_odd,
+                       long lcs, double* out, int project, hipStream_t s)
+{
+    const long V = (long)g.X * g.Y * g.Z * g.T;
+    hipLaunchKernelGGL(k_grad, grid1((V + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, (const double2*)x,
+                       (const double2*)lam, g, lk_even, lk_odd, lcs, (double2*)out, project);
+    return hipGetLastError();
+}
+
+} // namespace wd

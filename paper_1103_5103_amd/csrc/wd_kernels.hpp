@@ -1,0 +1,24 @@
+// Launchers of the libwdirac kernels (host side). Each returns the HIP error of the launch.
+#pragma once
+#include "wd_types.hpp"
+
+namespace wd {
+
+enum HopRed { RED_NONE = 0, RED_ZDOT = 1, RED_OUTX = 2, RED_NORM = 3 };
+enum SweepOp { OP_W = 0, OP_XR = 1, OP_S = 2, OP_SHIFT = 3, OP_INIT = 4, OP_ACC = 5, OP_NORM = 6, OP_MSINIT = 7 };
+
+hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
+                      SysState* sys, int gated, hipStream_t s);
+hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long nblocks, SysState* sys, int gated,
+                        hipStream_t s);
+hipError_t launch_pack_spinor(int sf, const double* src, const Geo& g, SpinorRef even, SpinorRef odd, int gamma5,
+                              double scale, hipStream_t s);
+hipError_t launch_unpack_spinor(int sf, double* dst, const Geo& g, SpinorRef even, SpinorRef odd, int gamma5,
+                                double scale, hipStream_t s);
+hipError_t launch_pack_links(const double* U, const Geo& g, void* even, void* odd, long lcs, hipStream_t s);
+hipError_t launch_convert_links(int lf, const void* src, void* dst, int Vh, long lcs, hipStream_t s);
+hipError_t launch_lincomb(double* out, const double* const* ins, const double* c, int k, long ncomplex, hipStream_t s);
+hipError_t launch_grad(const double* x, const double* lam, const Geo& g, const void* lk_even, const void* lk_odd,
+                       long lcs, double* out, int project, hipStream_t s);
+
+} // namespace wd

@@ -1,0 +1,217 @@
+// Runtime pieces of libwdirac: device memory, workspace fields, link preparation, job-table
+// upload, launch helpers with optional HIP-event timing, and the thread-local error message.
+#include <cstring>
+#include <mutex>
+
+#include "wd_host.hpp"
+
+namespace wd {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+const std::string& last_error() { return g_last_error; }
+
+DevMem::DevMem(size_t n) : bytes(n)
+{
+    if (n == 0) return;
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        throw Error{WD_ERR_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
+    }
+}
+DevMem::~DevMem()
+{
+    if (p) (void)hipFree(p);
+}
+
+size_t field_bytes(int sf, int halves, long stride)
+{
+    size_t n = (size_t)16 * spinor_chunks(sf) * halves * stride;
+    if (sf == SF16) n += (size_t)4 * halves * stride;
+    return n;
+}
+
+int spinor_fmt_of(wd_prec p)
+{
+    switch (p) {
+    case WD_F64: return SF64;
+    case WD_F32: return SF32;
+    case WD_F16: return SF16;
+    default: throw Error{WD_ERR_UNSUPPORTED, "spinor storage must be F64, F32 or F16"};
+    }
+}
+
+int link_fmt_of(wd_prec p, int recon)
+{
+    if (recon != 12 && recon != 18) throw Error{WD_ERR_ARG, "recon must be 12 or 18"};
+    if (p == WD_F64) return recon == 12 ? L64_12 : L64_18;
+    if (recon == 18) throw Error{WD_ERR_UNSUPPORTED, "18-real links are stored in FP64 only"};
+    switch (p) {
+    case WD_F32: return L32_12;
+    case WD_F16: return L16_12;
+    case WD_BF16: return LB16_12;
+    default: throw Error{WD_ERR_ARG, "bad link precision"};
+    }
+}
+
+// ---------------------------------------------------------------- pinned staging
+void* pinned(size_t bytes)
+{
+    static std::mutex mu;
+    static void* buf = nullptr;
+    static size_t cap = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if (bytes > cap) {
+        if (buf) (void)hipHostFree(buf);
+        size_t n = std::max(bytes, (size_t)1 << 20);
+        WD_CHECK_HIP(hipHostMalloc(&buf, n, hipHostMallocDefault));
+        cap = n;
+    }
+    return buf;
+}
+
+// ---------------------------------------------------------------- timing
+Timer& timer()
+{
+    static Timer t;
+    return t;
+}
+hipEvent_t Timer::get()
+{
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    WD_CHECK_HIP(hipEventCreate(&e));
+    return e;
+}
+void Timer::flush()
+{
+    for (auto& r : pending) {
+        WD_CHECK_HIP(hipEventSynchronize(r.b));
+        float t = 0;
+        WD_CHECK_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        ms[r.cls] += t;
+        bytes[r.cls] += r.bytes;
+        launches[r.cls] += 1;
+        pool.push_back(r.a);
+        pool.push_back(r.b);
+    }
+    pending.clear();
+}
+
+template <class J>
+void JobTable<J>::upload(hipStream_t s)
+{
+    size_t n = host.size() * sizeof(J);
+    if (!dev || dev->bytes < n) dev = std::make_shared<DevMem>(std::max(n, sizeof(J)));
+    void* stage = pinned(n);
+    std::memcpy(stage, host.data(), n);
+    WD_CHECK_HIP(hipMemcpyAsync(dev->p, stage, n, hipMemcpyHostToDevice, s));
+    // the staging buffer is reused by the next upload: wait for this copy
+    WD_CHECK_HIP(hipStreamSynchronize(s));
+    nblocks = 0;
+    for (auto& j : host) nblocks = std::max<long>(nblocks, (long)j.blk0 + j.nblk);
+}
+template struct JobTable<HopJob>;
+template struct JobTable<SweepJob>;
+
+void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>& t, SysState* sys, int gated,
+             hipStream_t s, double bytes)
+{
+    Timer& T = timer();
+    hipEvent_t a = nullptr, b = nullptr;
+    const int cls = sf == SF64 ? TK_HOP_F64 : TK_HOP_LO;
+    if (T.on) {
+        a = T.get();
+        b = T.get();
+        WD_CHECK_HIP(hipEventRecord(a, s));
+    }
+    WD_CHECK_HIP(launch_hop(sf, lf, dag, red, fin, t.d(), t.n(), t.nblocks, sys, gated, s));
+    if (T.on) {
+        WD_CHECK_HIP(hipEventRecord(b, s));
+        T.pending.push_back({cls, a, b, bytes});
+    }
+}
+
+void run_sweep(int op, int sfl, const JobTable<SweepJob>& t, SysState* sys, int gated, hipStream_t s, double bytes)
+{
+    Timer& T = timer();
+    hipEvent_t a = nullptr, b = nullptr;
+    if (T.on) {
+        a = T.get();
+        b = T.get();
+        WD_CHECK_HIP(hipEventRecord(a, s));
+    }
+    WD_CHECK_HIP(launch_sweep(op, sfl, t.d(), t.n(), t.nblocks, sys, gated, s));
+    if (T.on) {
+        WD_CHECK_HIP(hipEventRecord(b, s));
+        T.pending.push_back({TK_SWEEP, a, b, bytes});
+    }
+}
+
+} // namespace wd
+
+// ---------------------------------------------------------------- gauge handle
+using namespace wd;
+
+const void* wd_gauge::lk(int lf, int parity) const
+{
+    const DevMem* m = links[lf].get();
+    if (!m) throw Error{WD_ERR_ARG, "link format not prepared"};
+    size_t half = m->bytes / 2;
+    return (const char*)m->p + (size_t)parity * half;
+}
+
+static size_t link_bytes(int lf, long stride)
+{
+    return (size_t)2 * 8 * link_chunks(lf) * link_chunk_bytes(lf) * stride;
+}
+
+void wd_gauge::ensure_links(int lf, hipStream_t s)
+{
+    if (links[lf]) return;
+    auto m = std::make_unique<DevMem>(link_bytes(lf, geo.stride));
+    const size_t half = m->bytes / 2;
+    for (int p = 0; p < 2; p++)
+        WD_CHECK_HIP(launch_convert_links(lf, lk(L64_18, p), (char*)m->p + p * half, geo.Vh, geo.stride, s));
+    links[lf] = std::move(m);
+}
+
+Field& wd_gauge::field(const std::string& key, int sf, int halves)
+{
+    auto it = ws.find(key);
+    if (it != ws.end() && it->second.sf == sf && it->second.halves == halves) return it->second;
+    Field f;
+    f.sf = sf;
+    f.halves = halves;
+    f.stride = geo.stride;
+    f.mem = std::make_shared<DevMem>(field_bytes(sf, halves, geo.stride));
+    WD_CHECK_HIP(hipMemset(f.mem->p, 0, f.mem->bytes));
+    ws[key] = f;
+    return ws[key];
+}
+
+void* wd_gauge::rawbuf(const std::string& key, size_t bytes)
+{
+    auto it = raw.find(key);
+    if (it != raw.end() && it->second->bytes >= bytes) return it->second->p;
+    auto m = std::make_shared<DevMem>(bytes);
+    WD_CHECK_HIP(hipMemset(m->p, 0, m->bytes));
+    raw[key] = m;
+    return m->p;
+}
+
+size_t wd_gauge::device_bytes() const
+{
+    size_t n = 0;
+    for (auto& l : links)
+        if (l) n += l->bytes;
+    for (auto& kv : ws) n += kv.second.mem->bytes;
+    for (auto& kv : raw) n += kv.second->bytes;
+    return n;
+}

@@ -1,0 +1,775 @@
+// Solver drivers of libwdirac.
+//
+//  * eo_solve  : single-mass BiCGstab on the even-odd preconditioned system (Sec. 6.2.3, eq.
+//                eo2-eo4) for one or many systems at once. With mixed precision the Krylov vectors
+//                are stored in FP32 or FP16 and the operator uses FP16/BF16/FP32 12-real links;
+//                FP64 reliable updates (x_hi += x_lo, r = b_prec - M_prec x_hi in FP64) keep the
+//                true residual in step.
+//  * ms_solve  : BiCGstab-M (Sec. 6.1), FP64, full lattice; with one mass it is plain BiCGstab.
+//  * multimass : heaviest mass first, polynomial start guess (Sec. 6.2.1, Sec. 7).
+//
+// All kernels of an iteration are queued without host round trips: the BiCGstab scalars live on
+// the device and each kernel skips systems that are no longer RUNNING. The host reads the
+// per-system status every `poll` iterations and performs reliable updates, restarts and
+// convergence checks.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "wd_host.hpp"
+
+namespace wd {
+
+static double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static double spinor_site_bytes(int sf) { return sf == SF64 ? 192.0 : sf == SF32 ? 96.0 : 52.0; }
+static double link_site_bytes(int lf) { return 8.0 * link_chunks(lf) * link_chunk_bytes(lf); }
+
+// ---------------------------------------------------------------- device system records
+struct SysArray {
+    std::shared_ptr<DevMem> dev;
+    std::vector<SysState> h;
+    void alloc(int n)
+    {
+        h.assign(n, SysState{});
+        dev = std::make_shared<DevMem>(sizeof(SysState) * n);
+    }
+    SysState* d() const { return (SysState*)dev->p; }
+    void upload(hipStream_t s)
+    {
+        size_t n = sizeof(SysState) * h.size();
+        void* st = pinned(n);
+        std::memcpy(st, h.data(), n);
+        WD_CHECK_HIP(hipMemcpyAsync(dev->p, st, n, hipMemcpyHostToDevice, s));
+        WD_CHECK_HIP(hipStreamSynchronize(s));
+    }
+    void download(hipStream_t s)
+    {
+        size_t n = sizeof(SysState) * h.size();
+        void* st = pinned(n);
+        WD_CHECK_HIP(hipMemcpyAsync(st, dev->p, n, hipMemcpyDeviceToHost, s));
+        WD_CHECK_HIP(hipStreamSynchronize(s));
+        std::memcpy(h.data(), st, n);
+    }
+};
+
+static inline int nblk(long n) { return (int)((n + BLOCK - 1) / BLOCK); }
+
+static HopJob hop_job(const Geo& g, int parity, int sys, const SpinorRef& in, const SpinorRef& out,
+                      const void* links, long lcs, double c2)
+{
+    HopJob j;
+    std::memset(&j, 0, sizeof(j));
+    j.g = g;
+    j.parity = parity;
+    j.sys = sys;
+    j.in = in;
+    j.out = out;
+    j.links = links;
+    j.lcs = lcs;
+    j.c2 = c2;
+    j.nblk = nblk(g.Vh);
+    return j;
+}
+
+// Assign block ranges; jobs with the same sys form one reduction group.
+template <class J>
+static void layout(JobTable<J>& t)
+{
+    int b = 0;
+    std::map<int, int> group;
+    for (auto& j : t.host) {
+        j.blk0 = b;
+        b += j.nblk;
+        j.rblk0 = group[j.sys];
+        group[j.sys] += j.nblk;
+    }
+    for (auto& j : t.host) j.rnblk = group[j.sys];
+    t.nblocks = b;
+}
+
+static SweepJob sweep_job(int sys, long n)
+{
+    SweepJob j;
+    std::memset(&j, 0, sizeof(j));
+    j.sys = sys;
+    j.n = (int)n;
+    j.nblk = nblk(n);
+    return j;
+}
+
+static double hop_bytes(const JobTable<HopJob>& t, int sf, int lf, int extra_fields)
+{
+    double n = 0;
+    for (auto& j : t.host) n += (double)j.g.Vh;
+    return n * (2 * spinor_site_bytes(sf) + link_site_bytes(lf) + extra_fields * spinor_site_bytes(sf));
+}
+static double sweep_bytes(const JobTable<SweepJob>& t, double per_site)
+{
+    double n = 0;
+    for (auto& j : t.host) n += (double)j.n;
+    return n * per_site;
+}
+
+// ================================================================ even-odd BiCGstab (batched)
+
+struct EoSys {
+    wd_gauge* g;
+    double kappa, a;
+    const double* b;
+    double* x;
+    int slot;
+    Field B64, X64, BP, RH, T64, R64;
+    Field r, rh, s, w, As, Aw, tmp, xl;
+    double bb = 0;
+    bool done = false;
+    int restarts = 0, reliable = 0;
+    int final_status = WD_OK;
+    int iters = 0;
+    double true_rel = 0;
+    double t0 = 0, t1 = 0;
+};
+
+static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream_t st, int poll)
+{
+    const int n = (int)S.size();
+    const int SFL = P.mixed ? spinor_fmt_of(P.spinor_store) : SF64;
+    const int SFX = SFL == SF64 ? SF64 : SF32;
+    const int LFL = P.mixed ? link_fmt_of(P.link_store, P.recon) : L64_18;
+    const double t_start = now_s();
+
+    for (auto& e : S) {
+        e.g->ensure_links(LFL, st);
+        const std::string k = "eo" + std::to_string(e.slot) + ".";
+        e.B64 = e.g->field(k + "B64", SF64, 2);
+        e.X64 = e.g->field(k + "X64", SF64, 2);
+        e.R64 = e.g->field(k + "R64", SF64, 2);
+        e.BP = e.g->field(k + "BP", SF64, 1);
+        e.RH = e.g->field(k + "RH", SF64, 1);
+        e.T64 = e.g->field(k + "T64", SF64, 1);
+        e.r = e.g->field(k + "r", SFL, 1);
+        e.rh = e.g->field(k + "rh", SFL, 1);
+        e.s = e.g->field(k + "s", SFL, 1);
+        e.w = e.g->field(k + "w", SFL, 1);
+        e.As = e.g->field(k + "As", SFL, 1);
+        e.Aw = e.g->field(k + "Aw", SFL, 1);
+        e.tmp = e.g->field(k + "tmp", SFL, 1);
+        e.xl = e.g->field(k + "xl", SFX, 1);
+        e.a = 1.0 / (2.0 * e.kappa);
+    }
+
+    SysArray sys;
+    sys.alloc(n);
+    for (int i = 0; i < n; i++) {
+        EoSys& e = S[i];
+        SysState& q = sys.h[i];
+        std::memset(&q, 0, sizeof(q));
+        q.partials = (double*)e.g->rawbuf("eo" + std::to_string(e.slot) + ".partials",
+                                          sizeof(double) * NRED * (2 * e.g->geo.stride / BLOCK + 1));
+        q.maxit = P.max_iter;
+        q.mixed = P.mixed;
+        q.delta_rel2 = P.delta_reliable * P.delta_reliable;
+        q.target2 = -1.0;
+        q.status = ST_RUNNING;
+    }
+    sys.upload(st);
+
+    // ---- setup: pack b (and x0), b_prec, |b|^2
+    for (auto& e : S) {
+        WD_CHECK_HIP(launch_pack_spinor(SF64, e.b, e.g->geo, e.B64.half(0), e.B64.half(1), P.dagger, 1.0, st));
+        if (P.use_x0)
+            WD_CHECK_HIP(launch_pack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st));
+        else
+            WD_CHECK_HIP(hipMemsetAsync(e.X64.base(), 0, e.X64.mem->bytes, st));
+    }
+    JobTable<HopJob> Hbp, Hx1, Hx2, Hrec, Hres;
+    JobTable<SweepJob> Nb, Init, Acc;
+    for (int i = 0; i < n; i++) {
+        EoSys& e = S[i];
+        const Geo& g = e.g->geo;
+        // b_prec = a b_e + 1/2 D_eo b_o
+        HopJob j = hop_job(g, 0, i, e.B64.half(1), e.BP.all(), e.g->lk(L64_18, 0), e.g->lcs(), 0.5);
+        j.x0 = e.B64.half(0);
+        j.c0 = e.a;
+        Hbp.host.push_back(j);
+        // FP64 residual r_hi = b_prec - M_prec x_hi: T64 = D_oe x_e ; RH = b_prec - a^2 x_e + 1/4 D_eo T64
+        Hx1.host.push_back(hop_job(g, 1, i, e.X64.half(0), e.T64.all(), e.g->lk(L64_18, 1), e.g->lcs(), 1.0));
+        j = hop_job(g, 0, i, e.T64.all(), e.RH.all(), e.g->lk(L64_18, 0), e.g->lcs(), 0.25);
+        j.x0 = e.BP.all();
+        j.c0 = 1.0;
+        j.x1 = e.X64.half(0);
+        j.c1 = -e.a * e.a;
+        Hx2.host.push_back(j);
+        // odd half: x_o = (b_o + 1/2 D_oe x_e) / a
+        j = hop_job(g, 1, i, e.X64.half(0), e.X64.half(1), e.g->lk(L64_18, 1), e.g->lcs(), 0.5 / e.a);
+        j.x0 = e.B64.half(1);
+        j.c0 = 1.0 / e.a;
+        Hrec.host.push_back(j);
+        // true residual of the full system: R = b - a x + 1/2 D x, both parities
+        for (int p = 0; p < 2; p++) {
+            j = hop_job(g, p, i, e.X64.half(1 - p), e.R64.half(p), e.g->lk(L64_18, p), e.g->lcs(), 0.5);
+            j.x0 = e.B64.half(p);
+            j.c0 = 1.0;
+            j.x1 = e.X64.half(p);
+            j.c1 = -e.a;
+            Hres.host.push_back(j);
+        }
+        SweepJob sj = sweep_job(i, e.B64.nsites());
+        sj.f[R_F0] = e.B64.all();
+        Nb.host.push_back(sj);
+        sj = sweep_job(i, e.r.nsites());
+        sj.f[R_F0] = e.r.all();
+        sj.f[R_F1] = e.RH.all();
+        sj.f[R_F2] = e.rh.all();
+        sj.f[R_F3] = e.s.all();
+        sj.f[R_F4] = e.xl.all();
+        sj.flags = 1 | 2 | 4;
+        Init.host.push_back(sj);
+        sj = sweep_job(i, e.xl.nsites());
+        sj.f[R_F0] = e.X64.half(0);
+        sj.f[R_F1] = e.xl.all();
+        sj.flags = 1;
+        Acc.host.push_back(sj);
+    }
+    for (auto* t : {&Hbp, &Hx1, &Hx2, &Hrec, &Hres}) {
+        layout(*t);
+        t->upload(st);
+    }
+    for (auto* t : {&Nb, &Init, &Acc}) {
+        layout(*t);
+        t->upload(st);
+    }
+    run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, Hbp, sys.d(), 0, st, hop_bytes(Hbp, SF64, L64_18, 1));
+    run_sweep(OP_NORM, SF64, Nb, sys.d(), 0, st, sweep_bytes(Nb, 192));
+    sys.download(st);
+    for (int i = 0; i < n; i++) {
+        S[i].bb = sys.h[i].red[2];
+        // |b_prec - M_prec x_e| < tol (1/(2 kappa)) |b| is |b - M x| < tol |b| (odd residual vanishes)
+        sys.h[i].target2 = P.tol * P.tol * S[i].a * S[i].a * S[i].bb;
+        if (S[i].bb == 0.0) {  // zero source: x = 0
+            S[i].done = true;
+            sys.h[i].status = ST_CONVERGED;
+        }
+    }
+    sys.upload(st);
+    if (P.use_x0) {
+        run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, Hx1, sys.d(), 0, st, hop_bytes(Hx1, SF64, L64_18, 0));
+        run_hop(SF64, L64_18, false, RED_NORM, FIN_STORE, Hx2, sys.d(), 0, st, hop_bytes(Hx2, SF64, L64_18, 2));
+    } else {
+        for (auto& j : Init.host) j.f[R_F1] = S[j.sys].BP.all();
+        Init.upload(st);
+    }
+    run_sweep(OP_INIT, SFL, Init, sys.d(), 1, st, 0);
+    if (!P.use_x0) {
+        for (auto& j : Init.host) j.f[R_F1] = S[j.sys].RH.all();
+        Init.upload(st);
+    }
+    for (int i = 0; i < n; i++) S[i].t0 = t_start;
+
+    // ---- iteration tables
+    JobTable<HopJob> H1, H2, H3, H4;
+    JobTable<SweepJob> SW, SXR, SS;
+    for (int i = 0; i < n; i++) {
+        EoSys& e = S[i];
+        const Geo& g = e.g->geo;
+        const void* l0 = e.g->lk(LFL, 0);
+        const void* l1 = e.g->lk(LFL, 1);
+        H1.host.push_back(hop_job(g, 1, i, e.s.all(), e.tmp.all(), l1, e.g->lcs(), 1.0));
+        HopJob j = hop_job(g, 0, i, e.tmp.all(), e.As.all(), l0, e.g->lcs(), -0.25);
+        j.x0 = e.s.all();
+        j.c0 = e.a * e.a;
+        j.z = e.rh.all();
+        H2.host.push_back(j);
+        H3.host.push_back(hop_job(g, 1, i, e.w.all(), e.tmp.all(), l1, e.g->lcs(), 1.0));
+        j = hop_job(g, 0, i, e.tmp.all(), e.Aw.all(), l0, e.g->lcs(), -0.25);
+        j.x0 = e.w.all();
+        j.c0 = e.a * e.a;
+        H4.host.push_back(j);
+        SweepJob sj = sweep_job(i, e.r.nsites());
+        sj.f[R_F0] = e.w.all();
+        sj.f[R_F1] = e.r.all();
+        sj.f[R_F2] = e.As.all();
+        sj.f[R_F3] = e.r.all();
+        SW.host.push_back(sj);
+        sj = sweep_job(i, e.r.nsites());
+        sj.f[R_F0] = e.xl.all();
+        sj.f[R_F1] = e.r.all();
+        sj.f[R_F2] = e.s.all();
+        sj.f[R_F3] = e.w.all();
+        sj.f[R_F4] = e.Aw.all();
+        sj.f[R_F5] = e.rh.all();
+        sj.f[R_F6] = e.r.all();
+        SXR.host.push_back(sj);
+        sj = sweep_job(i, e.r.nsites());
+        sj.f[R_F0] = e.s.all();
+        sj.f[R_F1] = e.r.all();
+        sj.f[R_F2] = e.As.all();
+        sj.f[R_F3] = e.r.all();
+        SS.host.push_back(sj);
+    }
+    for (auto* t : {&H1, &H2, &H3, &H4}) {
+        layout(*t);
+        t->upload(st);
+    }
+    for (auto* t : {&SW, &SXR, &SS}) {
+        layout(*t);
+        t->upload(st);
+    }
+    const double bl = spinor_site_bytes(SFL), bx = spinor_site_bytes(SFX);
+    const double bH1 = hop_bytes(H1, SFL, LFL, 0), bH2 = hop_bytes(H2, SFL, LFL, 2), bH4 = hop_bytes(H4, SFL, LFL, 1);
+    const double bSW = sweep_bytes(SW, 3 * bl), bSXR = sweep_bytes(SXR, 2 * bx + 5 * bl), bSS = sweep_bytes(SS, 4 * bl);
+
+    auto iterate = [&]() {
+        run_hop(SFL, LFL, false, RED_NONE, FIN_STORE, H1, sys.d(), 1, st, bH1);
+        run_hop(SFL, LFL, false, RED_ZDOT, FIN_BETA, H2, sys.d(), 1, st, bH2);
+        run_sweep(OP_W, SFL, SW, sys.d(), 1, st, bSW);
+        run_hop(SFL, LFL, false, RED_NONE, FIN_STORE, H3, sys.d(), 1, st, bH1);
+        run_hop(SFL, LFL, false, RED_OUTX, FIN_CHI, H4, sys.d(), 1, st, bH4);
+        run_sweep(OP_XR, SFL, SXR, sys.d(), 1, st, bSXR);
+        run_sweep(OP_S, SFL, SS, sys.d(), 1, st, bSS);
+    };
+
+    // reliable update for a subset: x_hi += x_lo, r_hi = b_prec - M_prec x_hi, |r_hi|^2
+    auto reliable_update = [&](const std::vector<int>& ids) {
+        JobTable<SweepJob> A;
+        JobTable<HopJob> X1, X2;
+        for (int i : ids) {
+            A.host.push_back(Acc.host[i]);
+            X1.host.push_back(Hx1.host[i]);
+            X2.host.push_back(Hx2.host[i]);
+        }
+        layout(A);
+        layout(X1);
+        layout(X2);
+        A.upload(st);
+        X1.upload(st);
+        X2.upload(st);
+        run_sweep(OP_ACC, SFL, A, sys.d(), 0, st, sweep_bytes(A, 2 * 192 + 2 * bx));
+        run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, X1, sys.d(), 0, st, hop_bytes(X1, SF64, L64_18, 0));
+        run_hop(SF64, L64_18, false, RED_NORM, FIN_STORE, X2, sys.d(), 0, st, hop_bytes(X2, SF64, L64_18, 2));
+    };
+
+    int active = 0;
+    for (auto& e : S) active += !e.done;
+    long host_iters = 0;
+    const long host_cap = (long)P.max_iter + 16L * poll + 64;
+    while (active > 0) {
+        for (int k = 0; k < poll; k++) iterate();
+        host_iters += poll;
+        sys.download(st);
+        if (host_iters > host_cap) {
+            // the device never reported an exit state: stop instead of iterating forever
+            for (auto& e : S)
+                if (!e.done) {
+                    e.done = true;
+                    e.final_status = WD_ERR_NOCONV;
+                    e.t1 = now_s();
+                }
+            break;
+        }
+        std::vector<int> upd;
+        for (int i = 0; i < n; i++) {
+            if (S[i].done) continue;
+            int stt = sys.h[i].status;
+            if (stt == ST_RUNNING) continue;
+            if (stt == ST_NAN) {
+                S[i].done = true;
+                S[i].final_status = WD_ERR_NAN;
+                S[i].t1 = now_s();
+                active--;
+                continue;
+            }
+            upd.push_back(i);
+        }
+        if (upd.empty()) continue;
+        reliable_update(upd);
+        sys.download(st);
+        std::vector<int> cont, restart;
+        for (int i : upd) {
+            EoSys& e = S[i];
+            SysState& q = sys.h[i];
+            e.reliable++;
+            const double rr = q.red[2];
+            const int stt = q.status;
+            if (!std::isfinite(rr)) {
+                e.done = true;
+                e.final_status = WD_ERR_NAN;
+            } else if (rr <= q.target2) {
+                e.done = true;
+                e.final_status = WD_OK;
+            } else if (stt == ST_MAXIT || q.iter >= q.maxit) {
+                e.done = true;
+                e.final_status = WD_ERR_NOCONV;
+            } else if (stt == ST_BREAKDOWN) {
+                if (++e.restarts > 2) {
+                    e.done = true;
+                    e.final_status = WD_ERR_BREAKDOWN;
+                } else {
+                    restart.push_back(i);
+                }
+            } else {
+                cont.push_back(i);
+            }
+            if (e.done) {
+                e.t1 = now_s();
+                active--;
+            }
+        }
+        // new residual: keep rhat and s (reliable update) or restart with rhat = s = r (breakdown)
+        for (int pass = 0; pass < 2; pass++) {
+            const std::vector<int>& ids = pass == 0 ? cont : restart;
+            if (ids.empty()) continue;
+            JobTable<SweepJob> I;
+            for (int i : ids) {
+                SweepJob j = Init.host[i];
+                j.flags = pass == 0 ? 0 : (1 | 2);
+                I.host.push_back(j);
+            }
+            layout(I);
+            I.upload(st);
+            run_sweep(OP_INIT, SFL, I, sys.d(), 0, st, 0);
+        }
+    }
+
+    // ---- finish: odd half, FP64 true residual of the full system, unpack
+    run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, Hrec, sys.d(), 0, st, hop_bytes(Hrec, SF64, L64_18, 1));
+    run_hop(SF64, L64_18, false, RED_NORM, FIN_STORE, Hres, sys.d(), 0, st, hop_bytes(Hres, SF64, L64_18, 2));
+    for (auto& e : S)
+        WD_CHECK_HIP(launch_unpack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st));
+    sys.download(st);
+    for (int i = 0; i < n; i++) {
+        EoSys& e = S[i];
+        if (e.t1 == 0) e.t1 = now_s();
+        e.iters = sys.h[i].iter;
+        e.true_rel = e.bb > 0 ? std::sqrt(sys.h[i].red[2] / e.bb) : 0.0;
+    }
+}
+
+// ================================================================ BiCGstab-M (FP64, full lattice)
+
+static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* const* x, const double* b,
+                          const wd_solver_params& P, wd_solver_stats* stats, hipStream_t st, int poll)
+{
+    WD_REQUIRE(nk >= 1 && nk <= 32, "number of masses must be in 1..32");
+    const double t0 = now_s();
+    int base = 0;
+    for (int i = 1; i < nk; i++)
+        if (kappas[i] > kappas[base]) base = i;
+    const double a = 1.0 / (2.0 * kappas[base]);
+    const int ns = nk - 1;
+    std::vector<int> shift_of(nk, -1), mass_of_shift;
+    for (int i = 0; i < nk; i++)
+        if (i != base) {
+            shift_of[i] = (int)mass_of_shift.size();
+            mass_of_shift.push_back(i);
+        }
+
+    Field B = g->field("ms.B", SF64, 2), X = g->field("ms.X", SF64, 2), R0 = g->field("ms.R0", SF64, 2);
+    Field R1 = ns > 0 ? g->field("ms.R1", SF64, 2) : R0;
+    Field Sv = g->field("ms.S", SF64, 2), AS = g->field("ms.AS", SF64, 2), W = g->field("ms.W", SF64, 2);
+    Field AW = g->field("ms.AW", SF64, 2), RES = g->field("ms.RES", SF64, 2);
+    std::vector<Field> XS(ns), SS(ns);
+    for (int k = 0; k < ns; k++) {
+        XS[k] = g->field("ms.XS" + std::to_string(k), SF64, 2);
+        SS[k] = g->field("ms.SS" + std::to_string(k), SF64, 2);
+    }
+    const Geo& geo = g->geo;
+
+    SysArray sys;
+    sys.alloc(1);
+    SysState& q = sys.h[0];
+    std::memset(&q, 0, sizeof(q));
+    q.partials = (double*)g->rawbuf("ms.partials", sizeof(double) * NRED * (2 * geo.stride / BLOCK + 1));
+    q.maxit = P.max_iter;
+    q.mixed = 0;
+    q.nshift = ns;
+    q.target2 = -1;
+    q.beta_prev = make_double2(1.0, 0.0);
+    q.alpha = make_double2(0.0, 0.0);
+    std::vector<ShiftScal> sh(std::max(ns, 1));
+    std::vector<SpinorRef> shv(2 * std::max(ns, 1));
+    for (int k = 0; k < ns; k++) {
+        ShiftScal& z = sh[k];
+        std::memset(&z, 0, sizeof(z));
+        z.sigma = 1.0 / (2.0 * kappas[mass_of_shift[k]]) - a;
+        z.zeta_prev = z.zeta = z.rho = make_double2(1.0, 0.0);
+        z.active = 1;
+        shv[2 * k] = XS[k].all();
+        shv[2 * k + 1] = SS[k].all();
+    }
+    ShiftScal* d_sh = (ShiftScal*)g->rawbuf("ms.sh", sizeof(ShiftScal) * sh.size());
+    SpinorRef* d_shv = (SpinorRef*)g->rawbuf("ms.shv", sizeof(SpinorRef) * shv.size());
+    {
+        size_t n1 = sizeof(ShiftScal) * sh.size(), n2 = sizeof(SpinorRef) * shv.size();
+        char* stg = (char*)pinned(n1 + n2);
+        std::memcpy(stg, sh.data(), n1);
+        std::memcpy(stg + n1, shv.data(), n2);
+        WD_CHECK_HIP(hipMemcpyAsync(d_sh, stg, n1, hipMemcpyHostToDevice, st));
+        WD_CHECK_HIP(hipMemcpyAsync(d_shv, stg + n1, n2, hipMemcpyHostToDevice, st));
+        WD_CHECK_HIP(hipStreamSynchronize(st));
+    }
+    q.sh = d_sh;
+    q.shv = d_shv;
+    sys.upload(st);
+
+    WD_CHECK_HIP(launch_pack_spinor(SF64, b, geo, B.half(0), B.half(1), P.dagger, 1.0, st));
+    const long nsites = B.nsites();
+    JobTable<SweepJob> Init, SW, SXR, SEND;
+    SweepJob j = sweep_job(0, nsites);
+    j.f[R_F0] = R0.all();
+    j.f[R_F1] = B.all();
+    j.f[R_F2] = Sv.all();
+    j.f[R_F3] = Sv.all();
+    j.f[R_F4] = X.all();
+    Init.host.push_back(j);
+    j = sweep_job(0, nsites);
+    j.f[R_F0] = W.all();
+    j.f[R_F1] = R0.all();
+    j.f[R_F2] = AS.all();
+    j.f[R_F3] = R1.all();
+    SW.host.push_back(j);
+    j = sweep_job(0, nsites);
+    j.f[R_F0] = X.all();
+    j.f[R_F1] = R0.all();
+    j.f[R_F2] = Sv.all();
+    j.f[R_F3] = W.all();
+    j.f[R_F4] = AW.all();
+    j.f[R_F5] = B.all();
+    j.f[R_F6] = R1.all();
+    SXR.host.push_back(j);
+    j = sweep_job(0, nsites);
+    j.f[R_F0] = Sv.all();
+    j.f[R_F1] = R0.all();
+    j.f[R_F2] = AS.all();
+    j.f[R_F3] = R1.all();
+    j.f[R_F4] = W.all();
+    SEND.host.push_back(j);
+    JobTable<HopJob> HAs, HAw;
+    for (int p = 0; p < 2; p++) {
+        HopJob h = hop_job(geo, p, 0, Sv.half(1 - p), AS.half(p), g->lk(L64_18, p), g->lcs(), -0.5);
+        h.x0 = Sv.half(p);
+        h.c0 = a;
+        h.z = B.half(p);
+        HAs.host.push_back(h);
+        h = hop_job(geo, p, 0, W.half(1 - p), AW.half(p), g->lk(L64_18, p), g->lcs(), -0.5);
+        h.x0 = W.half(p);
+        h.c0 = a;
+        HAw.host.push_back(h);
+    }
+    for (auto* t : {&Init, &SW, &SXR, &SEND}) {
+        layout(*t);
+        t->upload(st);
+    }
+    for (auto* t : {&HAs, &HAw}) {
+        layout(*t);
+        t->upload(st);
+    }
+    run_sweep(OP_MSINIT, SF64, Init, sys.d(), 0, st, 0);
+    sys.download(st);
+    const double bb = sys.h[0].red[2];
+    sys.h[0].target2 = P.tol * P.tol * bb;
+    sys.h[0].shift_target2 = P.tol * P.tol * bb;
+    sys.h[0].beta_prev = make_double2(1.0, 0.0);
+    sys.h[0].alpha = make_double2(0.0, 0.0);
+    if (bb == 0.0) sys.h[0].status = ST_CONVERGED;
+    sys.upload(st);
+
+    const int endop = ns > 0 ? OP_SHIFT : OP_S;
+    const double bH = hop_bytes(HAs, SF64, L64_18, 2);
+    auto iterate = [&](int active_shifts) {
+        run_hop(SF64, L64_18, false, RED_ZDOT, FIN_BETA, HAs, sys.d(), 1, st, bH);
+        run_sweep(OP_W, SF64, SW, sys.d(), 1, st, sweep_bytes(SW, 3 * 192));
+        run_hop(SF64, L64_18, false, RED_OUTX, FIN_CHI, HAw, sys.d(), 1, st, bH - nsites * 192.0 / 2);
+        run_sweep(OP_XR, SF64, SXR, sys.d(), 1, st, sweep_bytes(SXR, 7 * 192));
+        run_sweep(endop, SF64, SEND, sys.d(), 1, st, sweep_bytes(SEND, (ns > 0 ? 6 : 4) * 192 + 4 * 192 * active_shifts));
+    };
+    int status = WD_OK;
+    int active_shifts = ns;
+    long host_iters = 0;
+    const long host_cap = (long)P.max_iter + 16L * poll + 64;
+    while (true) {
+        if (sys.h[0].status != ST_RUNNING) break;
+        if (host_iters > host_cap) break;  // no exit state reported by the device
+        for (int k = 0; k < poll; k++) iterate(active_shifts);
+        host_iters += poll;
+        sys.download(st);
+        if (ns > 0) {
+            size_t n1 = sizeof(ShiftScal) * ns;
+            void* stg = pinned(n1);
+            WD_CHECK_HIP(hipMemcpyAsync(stg, d_sh, n1, hipMemcpyDeviceToHost, st));
+            WD_CHECK_HIP(hipStreamSynchronize(st));
+            std::memcpy(sh.data(), stg, n1);
+            active_shifts = 0;
+            for (int k = 0; k < ns; k++) active_shifts += sh[k].active;
+        }
+    }
+    switch (sys.h[0].status) {
+    case ST_CONVERGED: status = WD_OK; break;
+    case ST_MAXIT: status = WD_ERR_NOCONV; break;
+    case ST_BREAKDOWN: status = WD_ERR_BREAKDOWN; break;
+    case ST_NAN: status = WD_ERR_NAN; break;
+    default: status = WD_ERR_NOCONV;
+    }
+    if (ns > 0) {
+        size_t n1 = sizeof(ShiftScal) * ns;
+        void* stg = pinned(n1);
+        WD_CHECK_HIP(hipMemcpyAsync(stg, d_sh, n1, hipMemcpyDeviceToHost, st));
+        WD_CHECK_HIP(hipStreamSynchronize(st));
+        std::memcpy(sh.data(), stg, n1);
+    }
+    const int iters = sys.h[0].iter;
+    const double t1 = now_s();
+
+    // true residual per mass and unpack
+    for (int i = 0; i < nk; i++) {
+        const Field& Xi = i == base ? X : XS[shift_of[i]];
+        const double ai = 1.0 / (2.0 * kappas[i]);
+        JobTable<HopJob> R;
+        for (int p = 0; p < 2; p++) {
+            HopJob h = hop_job(geo, p, 0, Xi.half(1 - p), RES.half(p), g->lk(L64_18, p), g->lcs(), 0.5);
+            h.x0 = B.half(p);
+            h.c0 = 1.0;
+            h.x1 = Xi.half(p);
+            h.c1 = -ai;
+            R.host.push_back(h);
+        }
+        layout(R);
+        R.upload(st);
+        run_hop(SF64, L64_18, false, RED_NORM, FIN_STORE, R, sys.d(), 0, st, 0);
+        WD_CHECK_HIP(launch_unpack_spinor(SF64, x[i], geo, Xi.half(0), Xi.half(1), P.dagger, 1.0, st));
+        sys.download(st);
+        if (stats) {
+            stats[i].iters = i == base ? iters : (sh[shift_of[i]].active ? iters : sh[shift_of[i]].conv_iter);
+            stats[i].reliable_updates = 0;
+            stats[i].true_rel_res = bb > 0 ? std::sqrt(sys.h[0].red[2] / bb) : 0.0;
+            stats[i].status = status;
+            stats[i].seconds = t1 - t0;
+        }
+    }
+    return (wd_status)status;
+}
+
+// ================================================================ entry points used by the C ABI
+
+wd_status solve_single(wd_gauge* g, double kappa, double* x, const double* b, const wd_solver_params& P,
+                       wd_solver_stats* stats, hipStream_t st)
+{
+    WD_REQUIRE(kappa > 0, "kappa must be positive");
+    if (!P.eo) {
+        WD_REQUIRE(!P.mixed, "mixed precision requires even-odd preconditioning");
+        WD_REQUIRE(!P.use_x0, "a start vector requires even-odd preconditioning");
+        double* xs[1] = {x};
+        return ms_solve(g, 1, &kappa, xs, b, P, stats, st, 4);
+    }
+    std::vector<EoSys> S(1);
+    S[0].g = g;
+    S[0].kappa = kappa;
+    S[0].b = b;
+    S[0].x = x;
+    S[0].slot = 0;
+    eo_solve(S, P, st, 4);
+    if (stats) {
+        stats->iters = S[0].iters;
+        stats->reliable_updates = S[0].reliable;
+        stats->status = S[0].final_status;
+        stats->true_rel_res = S[0].true_rel;
+        stats->seconds = S[0].t1 - S[0].t0;
+    }
+    return (wd_status)S[0].final_status;
+}
+
+wd_status solve_multishift(wd_gauge* g, int n, const double* kappas, double* const* x, const double* b,
+                           const wd_solver_params& P, wd_solver_stats* stats, hipStream_t st)
+{
+    for (int i = 0; i < n; i++) WD_REQUIRE(kappas[i] > 0, "kappa must be positive");
+    return ms_solve(g, n, kappas, x, b, P, stats, st, 4);
+}
+
+wd_status solve_batch(int nsys, const wd_system* sys, const wd_solver_params& P, wd_solver_stats* stats,
+                      hipStream_t st)
+{
+    WD_REQUIRE(nsys >= 1 && nsys <= 1024, "nsys must be in 1..1024");
+    WD_REQUIRE(P.eo, "batched solves use even-odd preconditioning");
+    std::vector<EoSys> S(nsys);
+    std::map<wd_gauge*, int> slots;
+    for (int i = 0; i < nsys; i++) {
+        WD_REQUIRE(sys[i].gauge && sys[i].b && sys[i].x, "null system entry");
+        WD_REQUIRE(sys[i].kappa > 0, "kappa must be positive");
+        S[i].g = sys[i].gauge;
+        S[i].kappa = sys[i].kappa;
+        S[i].b = sys[i].b;
+        S[i].x = sys[i].x;
+        S[i].slot = slots[sys[i].gauge]++;
+    }
+    eo_solve(S, P, st, 4);
+    wd_status worst = WD_OK;
+    for (int i = 0; i < nsys; i++) {
+        if (stats) {
+            stats[i].iters = S[i].iters;
+            stats[i].reliable_updates = S[i].reliable;
+            stats[i].status = S[i].final_status;
+            stats[i].true_rel_res = S[i].true_rel;
+            stats[i].seconds = S[i].t1 - S[i].t0;
+        }
+        if (S[i].final_status != WD_OK && worst == WD_OK) worst = (wd_status)S[i].final_status;
+    }
+    return worst;
+}
+
+wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* const* x, const double* b, int method,
+                          int guess, const wd_solver_params& P, wd_solver_stats* stats, hipStream_t st)
+{
+    WD_REQUIRE(n >= 1 && n <= 32, "number of masses must be in 1..32");
+    if (method == WD_METHOD_MULTISHIFT) return solve_multishift(g, n, kappas, x, b, P, stats, st);
+    WD_REQUIRE(method == WD_METHOD_SEQUENTIAL, "unknown method");
+    WD_REQUIRE(guess == WD_GUESS_NONE || guess == WD_GUESS_POLY, "unknown guess");
+    std::vector<int> order(n);
+    for (int i = 0; i < n; i++) order[i] = i;
+    // heaviest mass (smallest kappa) first (Sec. 7)
+    std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return kappas[p] < kappas[q]; });
+    double** d_ptrs = (double**)g->rawbuf("mm.ptrs", sizeof(double*) * 64);
+    double* d_coef = (double*)g->rawbuf("mm.coef", sizeof(double) * 64);
+    std::vector<int> done;
+    wd_status worst = WD_OK;
+    const long ncomplex = g->V * 12;
+    for (int idx : order) {
+        wd_solver_params Q = P;
+        Q.use_x0 = 0;
+        if (guess == WD_GUESS_POLY && !done.empty()) {
+            // Lagrange weights in m a = 1/(2 kappa) - 4 (Sec. 6.2.1), highest order available
+            const double m = 1.0 / (2.0 * kappas[idx]) - 4.0;
+            const int k = (int)done.size();
+            std::vector<double> c(k);
+            std::vector<const double*> ptr(k);
+            for (int jj = 0; jj < k; jj++) {
+                const double mj = 1.0 / (2.0 * kappas[done[jj]]) - 4.0;
+                double w = 1.0;
+                for (int ii = 0; ii < k; ii++) {
+                    if (ii == jj) continue;
+                    const double mi = 1.0 / (2.0 * kappas[done[ii]]) - 4.0;
+                    w *= (m - mi) / (mj - mi);
+                }
+                c[jj] = w;
+                ptr[jj] = x[done[jj]];
+            }
+            char* stg = (char*)pinned(64 * 16);
+            std::memcpy(stg, ptr.data(), sizeof(double*) * k);
+            std::memcpy(stg + 512, c.data(), sizeof(double) * k);
+            WD_CHECK_HIP(hipMemcpyAsync(d_ptrs, stg, sizeof(double*) * k, hipMemcpyHostToDevice, st));
+            WD_CHECK_HIP(hipMemcpyAsync(d_coef, stg + 512, sizeof(double) * k, hipMemcpyHostToDevice, st));
+            WD_CHECK_HIP(launch_lincomb(x[idx], (const double* const*)d_ptrs, d_coef, k, ncomplex, st));
+            WD_CHECK_HIP(hipStreamSynchronize(st));
+            Q.use_x0 = 1;
+        }
+        wd_status s = solve_single(g, kappas[idx], x[idx], b, Q, stats ? &stats[idx] : nullptr, st);
+        if (s != WD_OK && worst == WD_OK) worst = s;
+        done.push_back(idx);
+    }
+    return worst;
+}
+
+} // namespace wd

@@ -1,0 +1,101 @@
+// Structures shared by the host driver and the kernels of libwdirac.
+//
+// Every kernel launch works on a list of jobs held in device memory. A job is one (system,
+// parity) pair: the blocks of a launch are split over the jobs, so a single launch can advance
+// many independent systems of different lattice sizes at once (batched solves), and a
+// full-lattice operator is simply two jobs, one per output parity.
+//
+// Solver scalars live on the device (SysState), one record per system. Reductions are
+// deterministic: every block writes one partial sum, and the last block to finish (found with
+// an atomic ticket) adds the partials in a fixed order and then updates the scalars
+// ("finisher"). Kernels launched with gating skip systems whose status is not RUNNING, so a
+// whole chunk of iterations can be queued without host round trips.
+#pragma once
+#include "wd_device.hpp"
+
+namespace wd {
+
+enum SysStatus {
+    ST_RUNNING = 0,
+    ST_CONVERGED = 1,   // iterated residual below target: verify with an FP64 residual
+    ST_RELIABLE = 2,    // reliable update due
+    ST_BREAKDOWN = 3,
+    ST_NAN = 4,
+    ST_MAXIT = 5,
+};
+
+// Finisher kinds (what the last block does with the reduced sums)
+enum Fin {
+    FIN_STORE = 0,   // keep the sums in red[] for the host
+    FIN_BETA = 1,    // beta = -delta / <rhat, A s>            (+ shifted zeta, beta)
+    FIN_CHI = 2,     // chi = <A w, w> / <A w, A w>          (+ shifted chi, rho)
+    FIN_ALPHA = 3,   // delta' = <rhat, r>, |r|^2, alpha    (+ shifted alpha, freezing)
+    FIN_END = 4,     // end of iteration: commit status     (+ rotate shifted scalars)
+    FIN_RESTART = 5, // new residual: delta = <rhat, r>, |r|^2, status RUNNING
+};
+
+struct ShiftScal {
+    double sigma;
+    double2 zeta_prev, zeta, zeta_next;
+    double2 rho, rho_next;
+    double2 beta_s, chi_s, alpha_s;
+    int active;      // 1: updated this iteration, 0: frozen
+    int freeze;      // freeze after this iteration
+    int conv_iter;   // iteration at which the shift was frozen
+    int pad;
+};
+
+struct SysState {
+    unsigned counter;  // last-block ticket
+    int status;        // SysStatus
+    int pending;       // status committed at the end of the iteration
+    int iter;
+    int maxit;
+    int mixed;
+    int rsel;          // which residual buffer holds r_n (multi-shift keeps r_n and r_{n+1})
+    int nshift;
+    double2 delta, beta, chi, alpha, beta_prev;
+    double rr;         // |r|^2 of the iterated residual
+    double maxrr;      // max |r|^2 since the last reliable update
+    double target2;    // stop when rr <= target2
+    double delta_rel2; // reliable update when rr < delta_rel2 * maxrr
+    double shift_target2;
+    double red[NRED];  // last reduced sums
+    double* partials;  // [max blocks][NRED]
+    ShiftScal* sh;     // [nshift]
+    SpinorRef* shv;    // [2 * nshift]: x_sigma, s_sigma
+};
+
+struct HopJob {
+    Geo g;
+    int parity;  // output parity
+    int sys;     // SysState index (reduction group and gate)
+    int blk0;    // first block of this job in the launch
+    int nblk;
+    int rblk0;   // first block within the system's reduction group
+    int rnblk;   // blocks in the reduction group
+    SpinorRef in;        // input half field (the other parity)
+    SpinorRef out;       // output half field
+    SpinorRef x0, x1;    // epilogue terms (p == nullptr: absent)
+    SpinorRef z;         // partner of <z, out>
+    const void* links;   // the 8 links per site of this output parity
+    long lcs;            // link chunk stride
+    double c0, c1, c2;   // out = c0 x0 + c1 x1 + c2 * hop
+};
+
+// Roles of the fields of a sweep job
+enum SweepRole { R_F0 = 0, R_F1, R_F2, R_F3, R_F4, R_F5, R_F6, R_F7, NROLE };
+
+struct SweepJob {
+    int sys;
+    int n;       // sites
+    int blk0;
+    int nblk;
+    int rblk0;
+    int rnblk;
+    int flags;   // op-specific
+    int pad;
+    SpinorRef f[NROLE];
+};
+
+} // namespace wd

@@ -1,0 +1,289 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Tolerances: FP64 operator results agree to rounding (relative 1e-14; only the summation order
+differs). Solves are compared through the oracle's FP64 true residual |b - M x|/|b|, which must
+be below the requested tolerance (1e-10 for FP64 solves, 1e-8 for mixed precision), and through
+the distance to the oracle's own solution, bounded by the condition number times the tolerance.
+"""
+import numpy as np
+import pytest
+import torch
+
+import lattice_inputs as li
+import oracle
+import paper_1103_5103_amd as wd
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ operator
+
+@pytest.mark.parametrize("dims,anti", [((2, 2, 2, 2), 1), ((4, 4, 4, 4), 1), ((4, 2, 6, 4), 1), ((4, 4, 4, 8), 0),
+                                       ((8, 8, 8, 8), 1), ((6, 4, 2, 10), 1), ((16, 8, 8, 16), 1)])
+def test_apply_parity(dims, anti):
+    _say("apply", dims, anti)
+    U = li.random_links(dims, 1.0, 1000)
+    psi = li.gaussian_field(dims, 2000)
+    g = wd.wd_gauge_create(_t(U), antiperiodic=bool(anti))
+    pd = _t(psi)
+    for kappa in (0.12, 0.135):
+        out = _n(wd.wd_apply(g, kappa, pd))
+        assert _rel(out, oracle.apply(U, kappa, psi, antiperiodic=anti)) < 1e-14
+        outd = _n(wd.wd_apply_dag(g, kappa, pd))
+        assert _rel(outd, oracle.apply(U, kappa, psi, dag=True, antiperiodic=anti)) < 1e-14
+    g.close()
+
+
+def test_apply_free_field_closed_form():
+    """U = 1 plane wave: M e^{ip.n} u = e^{ip.n} u (W + i sum sin p gamma) (antiperiodic time)."""
+    dims = (8, 4, 4, 8)
+    X, Y, Z, T = dims
+    kappa = 0.12
+    ma = 1 / (2 * kappa) - 4
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    p = [2 * np.pi * 3 / X, 2 * np.pi / Y, 0.0, 5 * np.pi / T]
+    u = (np.arange(12).reshape(3, 4) + 0.5j).astype(np.complex128)
+    phase = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))
+    K = (ma + sum(1 - np.cos(v) for v in p)) * np.eye(4) + 1j * sum(np.sin(p[m]) * oracle.gamma(m) for m in range(4))
+    g = wd.wd_gauge_create(_t(li.unit_links(dims)))
+    out = _n(wd.wd_apply(g, kappa, _t(phase[..., None, None] * u)))
+    assert _rel(out, phase[..., None, None] * (u @ K)) < 1e-13
+    g.close()
+
+
+# ------------------------------------------------------------------ single-mass solves
+
+def test_bicgstab_plain_fp64_4444():
+    """Plain FP64 BiCGstab without even-odd on 4^4, eps 0.3, kappa 0.12, to 1e-10."""
+    dims = (4, 4, 4, 4)
+    U = li.random_links(dims, 0.3, 1000)
+    b = li.gaussian_field(dims, 2000)
+    g = wd.wd_gauge_create(_t(U))
+    x, st = wd.bicgstab_solve(g, 0.12, _t(b), p=wd.params(tol=1e-10, mixed=False, eo=False))
+    xo, ito, sto, _ = oracle.bicgstab(U, 0.12, b, tol=1e-10)
+    xn = _n(x)
+    res = oracle.true_residual(U, 0.12, xn, b)
+    _say("plain fp64", st, "oracle iters", ito, "residual", res)
+    assert res < 1e-10
+    assert abs(st["iters"] - ito) <= 1
+    assert _rel(xn, xo) < 1e-8
+    g.close()
+
+
+def test_dense_lu_2444():
+    dims = (2, 2, 2, 2)
+    U = li.random_links(dims, 1.0, 1003)
+    b = li.gaussian_field(dims, 2003)
+    g = wd.wd_gauge_create(_t(U))
+    for kappa in (0.12, 0.13):
+        x_lu = np.linalg.solve(oracle.dense_matrix(U, kappa), b.ravel()).reshape(b.shape)
+        for eo in (False, True):
+            x, st = wd.bicgstab_solve(g, kappa, _t(b), p=wd.params(tol=1e-13, mixed=False, eo=eo))
+            assert _rel(_n(x), x_lu) < 1e-11, (kappa, eo, st)
+    g.close()
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (8, 8, 8, 8)])
+def test_bicgstab_eo_fp64(dims):
+    U = li.random_links(dims, 1.0, 1004)
+    b = li.gaussian_field(dims, 2004)
+    g = wd.wd_gauge_create(_t(U))
+    kappa = 0.13
+    x, st = wd.bicgstab_solve(g, kappa, _t(b), p=wd.params(tol=1e-10, mixed=False, eo=True))
+    xo, ito, _, _ = oracle.bicgstab_eo(U, kappa, b, tol=1e-10)
+    res = oracle.true_residual(U, kappa, _n(x), b)
+    _say("eo fp64", dims, st, "oracle iters", ito, "residual", res)
+    assert res < 1e-10
+    assert abs(st["iters"] - ito) <= 1
+    assert abs(st["true_rel_res"] - res) < 1e-3 * res + 1e-14
+    g.close()
+
+
+@pytest.mark.parametrize("spinor,links", [("f32", "f16"), ("f32", "bf16"), ("f32", "f32"), ("f16", "f16")])
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 4, 4, 10)])
+def test_bicgstab_eo_mixed(dims, spinor, links):
+    U = li.random_links(dims, 1.0, 1005)
+    b = li.gaussian_field(dims, 2005)
+    g = wd.wd_gauge_create(_t(U))
+    kappa = 0.13
+    x, st = wd.bicgstab_solve(g, kappa, _t(b), p=wd.params(tol=1e-8, spinor=spinor, links=links))
+    res = oracle.true_residual(U, kappa, _n(x), b)
+    _say("eo mixed", dims, spinor, links, st, "oracle residual", res)
+    assert st["status"] == 0
+    assert res < 1e-8
+    assert st["reliable_updates"] >= 1
+    g.close()
+
+
+def test_bicgstab_dagger_solves_adjoint():
+    dims = (4, 4, 4, 8)
+    U = li.random_links(dims, 1.0, 1006)
+    b = li.gaussian_field(dims, 2006)
+    g = wd.wd_gauge_create(_t(U))
+    kappa = 0.125
+    for mixed in (False, True):
+        x, st = wd.bicgstab_solve(g, kappa, _t(b), p=wd.params(tol=1e-10 if not mixed else 1e-8, mixed=mixed,
+                                                                dagger=True))
+        r = b - oracle.apply(U, kappa, _n(x), dag=True)
+        assert np.linalg.norm(r) / np.linalg.norm(b) < (1e-10 if not mixed else 1e-8)
+    g.close()
+
+
+def test_start_vector_is_used():
+    dims = (8, 8, 8, 8)
+    U = li.random_links(dims, 1.0, 1007)
+    b = li.gaussian_field(dims, 2007)
+    kappa = 0.128
+    g = wd.wd_gauge_create(_t(U))
+    xo, _, _, _ = oracle.bicgstab(U, kappa, b, tol=1e-12, eo=True)
+    x0 = _t(xo * (1 + 1e-4))
+    x, st = wd.bicgstab_solve(g, kappa, _t(b), x=x0, p=wd.params(tol=1e-8, use_x0=True))
+    x1, st1 = wd.bicgstab_solve(g, kappa, _t(b), p=wd.params(tol=1e-8))
+    assert oracle.true_residual(U, kappa, _n(x), b) < 1e-8
+    assert st["iters"] < st1["iters"]
+    g.close()
+
+
+# ------------------------------------------------------------------ multi-shift and multi-mass
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (8, 8, 8, 8)])
+def test_bicgstab_m_parity(dims):
+    U = li.random_links(dims, 1.0, 1001)
+    b = li.gaussian_field(dims, 2001)
+    kappas = [0.120, 0.122, 0.124, 0.126, 0.128, 0.130]
+    g = wd.wd_gauge_create(_t(U))
+    xs, sts = wd.bicgstab_m_solve(g, kappas, _t(b), p=wd.params(tol=1e-10, mixed=False, eo=False))
+    xo, ito, sto, conv = oracle.bicgstab_m(U, kappas, b, tol=1e-10)
+    _say("bicgstab-m", dims, [s["iters"] for s in sts], "oracle", conv)
+    for k, x, s, xr, c in zip(kappas, xs, sts, xo, conv):
+        res = oracle.true_residual(U, k, _n(x), b)
+        assert res < 2e-10, (k, res)
+        assert abs(s["true_rel_res"] - res) < 1e-3 * res + 1e-14
+        assert _rel(_n(x), xr) < 1e-8
+        assert abs(s["iters"] - c) <= 1
+    g.close()
+
+
+def test_multimass_sequential_poly_guess():
+    dims = (8, 8, 8, 8)
+    U = li.random_links(dims, 1.0, 1001)
+    b = li.gaussian_field(dims, 2001)
+    kappas = [0.120, 0.122, 0.124, 0.126, 0.128, 0.130]
+    g = wd.wd_gauge_create(_t(U))
+    bd = _t(b)
+    xs, sts = wd.wd_multimass_solve(g, kappas, bd, guess=wd.WD_GUESS_POLY)
+    xs0, sts0 = wd.wd_multimass_solve(g, kappas, bd, guess=wd.WD_GUESS_NONE)
+    for k, x in zip(kappas, xs):
+        assert oracle.true_residual(U, k, _n(x), b) < 1e-8
+    it, it0 = sum(s["iters"] for s in sts), sum(s["iters"] for s in sts0)
+    _say("multimass poly", it, "none", it0)
+    assert it < it0
+    xm, stm = wd.wd_multimass_solve(g, kappas, bd, method=wd.WD_METHOD_MULTISHIFT,
+                                    p=wd.params(tol=1e-8, mixed=False, eo=False))
+    for k, x in zip(kappas, xm):
+        assert oracle.true_residual(U, k, _n(x), b) < 1.5e-8
+    g.close()
+
+
+def test_batch_uneven_lattices():
+    cases = [((8, 8, 8, 8), 1010), ((4, 4, 4, 8), 1011), ((6, 6, 6, 6), 1012)]
+    kappas = [0.124, 0.130]
+    systems, refs, gauges = [], [], []
+    for dims, seed in cases:
+        U = li.random_links(dims, 1.0, seed)
+        g = wd.wd_gauge_create(_t(U))
+        gauges.append(g)
+        for s in range(2):
+            b = li.point_source(dims, spin=s, colour=s)
+            for k in kappas:
+                systems.append((g, k, _t(b), torch.zeros(g.field_shape, dtype=torch.complex128, device=DEV)))
+                refs.append((U, k, b))
+    sts = wd.wd_batch_solve(systems)
+    for (g, k, bd, x), (U, kk, b), s in zip(systems, refs, sts):
+        res = oracle.true_residual(U, kk, _n(x), b)
+        assert s["status"] == 0 and res < 1e-8, (s, res)
+    # the batched result equals the one-at-a-time result
+    g, k, bd, x = systems[0]
+    x1, _ = wd.bicgstab_solve(g, k, bd)
+    assert _rel(_n(x), _n(x1)) < 1e-6
+    for g in gauges:
+        g.close()
+
+
+# ------------------------------------------------------------------ gradient
+
+@pytest.mark.parametrize("dims,anti", [((4, 4, 4, 8), 1), ((2, 2, 2, 4), 1), ((4, 2, 2, 4), 0)])
+def test_gauge_grad_parity(dims, anti):
+    U = li.random_links(dims, 1.0, 1020)
+    x = li.gaussian_field(dims, 2020)
+    lam = li.gaussian_field(dims, 2021)
+    g = wd.wd_gauge_create(_t(U), antiperiodic=bool(anti))
+    G = _n(wd.wd_gauge_grad(g, _t(x), _t(lam)))
+    Gr = oracle.gauge_grad(x, lam, antiperiodic=anti)
+    assert _rel(G, Gr) < 1e-14
+    F = _n(wd.wd_gauge_grad(g, _t(x), _t(lam), project=True))
+    assert _rel(F, oracle.su3_project(U, Gr)) < 1e-13
+    g.close()
+
+
+def test_autograd_matches_oracle():
+    dims = (4, 4, 4, 4)
+    kappa = 0.125
+    U = li.random_links(dims, 1.0, 1030)
+    b = li.gaussian_field(dims, 2030)
+    eta = li.gaussian_field(dims, 2031)
+    Ud = _t(U).requires_grad_(True)
+    bd = _t(b).requires_grad_(True)
+    x = wd.wilson_solve(Ud, bd, kappa, params=wd.params(tol=1e-13, mixed=False))
+    loss = torch.real(torch.sum(torch.conj(_t(eta)) * x))
+    loss.backward()
+    G5 = np.diag([1, 1, -1, -1]).astype(np.complex128)
+    xo, _, _, _ = oracle.bicgstab(U, kappa, b, tol=1e-14)
+    lg, _, _, _ = oracle.bicgstab(U, kappa, eta @ G5, tol=1e-14)
+    lam = lg @ G5
+    assert _rel(_n(bd.grad), lam) < 1e-10
+    assert _rel(_n(Ud.grad), oracle.gauge_grad(xo, lam)) < 1e-10
+
+
+# ------------------------------------------------------------------ error paths
+
+def test_error_codes():
+    dims = (4, 4, 4, 4)
+    U = li.random_links(dims, 1.0, 1040)
+    with pytest.raises(ValueError):
+        wd.wd_gauge_create(_t(U)[:, :, :, :, :3])
+    g = wd.wd_gauge_create(_t(U))
+    b = _t(li.gaussian_field(dims, 2040))
+    x, st = wd.bicgstab_solve(g, 0.125, b, p=wd.params(tol=1e-12, max_iter=1), raise_on_fail=False)
+    assert st["status"] == 4 and st["iters"] >= 1
+    with pytest.raises(wd.WdError):
+        wd.bicgstab_solve(g, 0.125, b, p=wd.params(tol=1e-12, max_iter=1))
+    z, stz = wd.bicgstab_solve(g, 0.125, torch.zeros_like(b))
+    assert stz["status"] == 0 and float(torch.abs(z).max()) == 0.0
+    with pytest.raises(wd.WdError):
+        wd.bicgstab_solve(g, -1.0, b)
+    g.close()
+
+
+def test_odd_extent_rejected():
+    U = torch.zeros((4, 4, 4, 4, 3, 3, 3), dtype=torch.complex128, device=DEV)
+    with pytest.raises(wd.WdError) as e:
+        wd.wd_gauge_create(U)
+    assert e.value.code == 1
