@@ -1,0 +1,207 @@
+"""Benchmark: multi-mass Wilson-Dirac solves on one MI355X.
+
+One step is one pass of the whole hot path over the 32^3x64 workload: the sequential
+single-mass even-odd mixed-precision BiCGstab for all 8 masses (FP16 12-real links, FP32 spinors,
+FP64 reductions and reliable updates, polynomial start guess, heaviest mass first), followed by
+the FP64 BiCGstab-M solve of the same 8 masses on the full lattice, both to relative residual
+1e-8. Inputs are synthetic: near-Haar random SU(3) links exp(i H) and one complex Gaussian source,
+seeded; they stand in for the paper's quenched ensemble, which is not available.
+
+The reported value is the low-precision dslash (even-odd hop) throughput: algorithmic bytes of
+every hop launch in the timed steps divided by their durations, measured with HIP events on the
+launch stream. Per output site a hop moves the input spinor, the output spinor and 8 links
+(96 + 96 + 8 x 24 = 384 B with FP32 spinors and FP16 12-real links) plus the epilogue fields it
+reads. The CPU baseline is the plain FP64 oracle on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 32x64|16x32] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "dslash HBM GB/s; multi-mass solve sec @ rel.res 1e-8, mixed/batched vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "32x64": dict(dims=(32, 32, 32, 64), kappas=[0.120 + 0.002 * k for k in range(8)], eps=1.0, link_seed=1002,
+                  src_seed=2002, links="f16", spinor="f32", delta=1e-3,
+                  name="32^3x64 even-odd Wilson, 8 masses kappa 0.120..0.134, near-Haar SU(3) links, FP16 12-real "
+                       "links, FP32 spinors, FP64 reliable updates, 1 Gaussian source"),
+    "16x32": dict(dims=(16, 16, 16, 32), kappas=[0.120, 0.122, 0.124, 0.126, 0.128, 0.130], eps=1.0,
+                  link_seed=1001, src_seed=2001, links="f16", spinor="f16", delta=0.1,
+                  name="16^3x32 even-odd Wilson, 6 masses kappa 0.120..0.130, near-Haar SU(3) links, FP16 12-real "
+                       "links, FP16 spinors, FP64 reliable updates, 1 Gaussian source"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(U, b, kappas, dims, budget_s=12.0):
+    """Time the plain FP64 oracle on the host: its hopping term (the dslash) for about
+    budget_s seconds, converted to the same algorithmic-bytes convention (FP64 full lattice:
+    192 B in + 192 B out + 4 x 2 x 72 B links per site = 960 B/site)."""
+    import numpy as np
+
+    import oracle
+
+    V = int(np.prod(dims))
+    oracle.hopping(U, b)  # page in
+    n, t0 = 0, time.perf_counter()
+    while True:
+        oracle.hopping(U, b)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = (time.perf_counter() - t0) / n
+    return {
+        "value": round(V * 960.0 / dt / 1e9, 3),
+        "unit": "GB/s",
+        "cores": oracle.get_threads(),
+        "kind": "oracle",
+        "sample": f"{n} applications of the FP64 oracle hopping term on the full {dims[0]}^3x{dims[3]} lattice "
+                  f"({dt * 1e3:.1f} ms each), bytes counted as 960 B/site",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="32x64", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--poll", type=int, default=0, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import lattice_inputs as li
+    import paper_1103_5103_amd as wd
+
+    W = WORKLOADS[args.workload]
+    dims, kappas = W["dims"], W["kappas"]
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    U = li.random_links(dims, W["eps"], W["link_seed"])
+    b = li.gaussian_field(dims, W["src_seed"])
+    log(f"inputs {dims} generated in {time.perf_counter() - t0:.1f}s")
+    Ud = torch.from_numpy(U).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    p_mixed = wd.params(tol=1e-8, spinor=W["spinor"], links=W["links"], delta=W["delta"])
+    p_f64 = wd.params(tol=1e-8, mixed=False, eo=False)
+    g = wd.wd_gauge_create(Ud, hint=p_mixed)
+    del Ud
+    xs = [torch.zeros_like(bd) for _ in kappas]
+    xm = [torch.zeros_like(bd) for _ in kappas]
+
+    def step():
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        _, st_mixed = wd.wd_multimass_solve(g, kappas, bd, method=wd.WD_METHOD_SEQUENTIAL, guess=wd.WD_GUESS_POLY,
+                                            xs=xs, p=p_mixed)
+        torch.cuda.synchronize()
+        m = time.perf_counter()
+        _, st_ms = wd.bicgstab_m_solve(g, kappas, bd, xs=xm, p=p_f64)
+        torch.cuda.synchronize()
+        e = time.perf_counter()
+        return (m - a, e - m, st_mixed, st_ms)
+
+    for i in range(args.warmup):
+        r = step()
+        log(f"warmup {i}: mixed sequential {r[0]:.4f}s, FP64 BiCGstab-M {r[1]:.4f}s")
+    wd.timing_reset()
+    wd.timing_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    results = []
+    for i in range(args.steps):
+        results.append(step())
+        log(f"step {i}: mixed sequential {results[-1][0]:.4f}s, FP64 BiCGstab-M {results[-1][1]:.4f}s")
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    hop_ms, hop_n, hop_bytes = wd.timing_get(0)
+    f64_ms, f64_n, f64_bytes = wd.timing_get(1)
+    sw_ms, sw_n, sw_bytes = wd.timing_get(2)
+    wd.timing_enable(False)
+
+    hop_gbs = hop_bytes / (hop_ms * 1e-3) / 1e9 if hop_ms > 0 else 0.0
+    ms_per_step = (t_end - t_start) / args.steps * 1e3
+    t_mixed = float(np.median([r[0] for r in results]))
+    t_ms = float(np.median([r[1] for r in results]))
+    st_mixed, st_ms = results[-1][2], results[-1][3]
+    V = int(np.prod(dims))
+    out = {
+        "metric": METRIC,
+        "value": round(hop_gbs, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": W["name"],
+            "lattice": list(dims),
+            "kappas": [round(k, 6) for k in kappas],
+            "tol": 1e-8,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(hop_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(hop_gbs / HBM_PEAK_GBS, 4),
+            "traffic": None,
+        },
+        "hop_launches": hop_n,
+        "hop_avg_us": round(hop_ms / max(hop_n, 1) * 1e3, 2),
+        "hop_bytes_per_launch": round(hop_bytes / max(hop_n, 1)),
+        "fp64_hop_GBps": round(f64_bytes / (f64_ms * 1e-3) / 1e9, 1) if f64_ms > 0 else None,
+        "sweep_GBps": round(sw_bytes / (sw_ms * 1e-3) / 1e9, 1) if sw_ms > 0 else None,
+        "solve_s_mixed_sequential": round(t_mixed, 5),
+        "solve_s_fp64_multishift": round(t_ms, 5),
+        "speedup_mixed_vs_multishift": round(t_ms / t_mixed, 3) if t_mixed > 0 else None,
+        "iters_mixed": [s["iters"] for s in st_mixed],
+        "reliable_updates": [s["reliable_updates"] for s in st_mixed],
+        "iters_multishift": [s["iters"] for s in st_ms],
+        "true_rel_res_mixed": [float(f"{s['true_rel_res']:.3e}") for s in st_mixed],
+        "true_rel_res_multishift": [float(f"{s['true_rel_res']:.3e}") for s in st_ms],
+        "device_bytes": g.device_bytes(),
+    }
+    if not args.no_cpu:
+        try:
+            import oracle
+
+            out["cpu_baseline"] = cpu_baseline(U, b, kappas, dims)
+            # parity of the benchmark's own result: FP64 oracle residual of two masses
+            chk = {}
+            for i in (0, len(kappas) - 1):
+                chk[f"{kappas[i]:.3f}"] = float(f"{oracle.true_residual(U, kappas[i], xs[i].cpu().numpy(), b):.3e}")
+            out["oracle_true_rel_res_mixed"] = chk
+        except Exception as e:  # the CPU leg must not hide the GPU number
+            out["cpu_baseline"] = {"error": repr(e)}
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -181,7 +181,8 @@ wd_status wd_last_error(char* buf, size_t n);
  * Kernel timing (measurement support, not part of the method). When enabled, the library
  * brackets each launch of the named kernel classes with HIP events on the launch stream and
  * accumulates their durations; reading the totals synchronises the recorded events.
- * class: 0 = low-precision even-odd hop, 1 = FP64 hop, 2 = fused vector sweeps.
+ * class: 0 = low-precision even-odd hop, 1 = FP64 hop, 2 = fused vector sweeps,
+ *        3 = the small finisher kernels that complete the reductions.
  */
 void wd_timing_enable(int on);
 void wd_timing_reset(void);

@@ -66,15 +66,15 @@ struct Field {
 size_t field_bytes(int sf, int halves, long stride);
 
 // ---------------------------------------------------------------- timing
-enum { TK_HOP_LO = 0, TK_HOP_F64 = 1, TK_SWEEP = 2, NTK = 3 };
+enum { TK_HOP_LO = 0, TK_HOP_F64 = 1, TK_SWEEP = 2, TK_FINISH = 3, NTK = 4 };
 struct Timer {
     bool on = false;
     struct Rec { int cls; hipEvent_t a, b; double bytes; };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
-    double ms[NTK] = {0, 0, 0};
-    double bytes[NTK] = {0, 0, 0};
-    long launches[NTK] = {0, 0, 0};
+    double ms[NTK] = {0, 0, 0, 0};
+    double bytes[NTK] = {0, 0, 0, 0};
+    long launches[NTK] = {0, 0, 0, 0};
     hipEvent_t get();
     void flush();
 };
@@ -85,10 +85,13 @@ template <class J>
 struct JobTable {
     std::vector<J> host;
     std::shared_ptr<DevMem> dev;
+    std::vector<FinJob> fin;  // one entry per system, for the finisher kernel
     long nblocks = 0;
     void upload(hipStream_t s);
     int n() const { return (int)host.size(); }
     const J* d() const { return (const J*)dev->p; }
+    const FinJob* fin_d() const { return (const FinJob*)((const char*)dev->p + fin_offset()); }
+    size_t fin_offset() const { return (host.size() * sizeof(J) + 255) / 256 * 256; }
 };
 
 // ---------------------------------------------------------------- gauge handle

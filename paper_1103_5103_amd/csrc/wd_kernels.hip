@@ -10,7 +10,36 @@
 //  * k_grad    : link derivative of Re<eta, M^{-1} b> (outer products of projected spinors).
 #include "wd_kernels.hpp"
 
+// Occupancy hints of the hop kernel (minimum waves per SIMD; 0 lets the compiler choose) and
+// the XCD-aware block order, selectable at build time.
+#ifndef WD_HOP_WAVES_LO
+#define WD_HOP_WAVES_LO 0
+#endif
+#ifndef WD_HOP_WAVES_64
+#define WD_HOP_WAVES_64 0
+#endif
+#ifndef WD_XCD_REMAP
+#define WD_XCD_REMAP 1
+#endif
+// Directions whose loads may be scheduled together in the hop (8: all, 1: one at a time). A
+// scheduling barrier between groups bounds the live registers instead of spilling.
+#ifndef WD_HOP_GROUP_LO
+#define WD_HOP_GROUP_LO 8
+#endif
+#ifndef WD_HOP_GROUP_64
+#define WD_HOP_GROUP_64 8
+#endif
+
 namespace wd {
+
+// MI355X has 8 XCDs, each with its own L2; consecutive workgroups go to consecutive XCDs. This
+// bijection on [0, nb) hands each XCD one contiguous eighth of the blocks, so the neighbour
+// sites a block gathers were mostly loaded by blocks of the same XCD and hit in its L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
 
 // ================================================================ finishers
 
@@ -110,42 +139,38 @@ __device__ void finish(SysState* S, const double* tot)
     }
 }
 
-// Block reduction of NR partial sums, ticket, and (in the last block of the system's
-// reduction group) a fixed-order final sum followed by the finisher.
-template <int NR, int FIN>
-__device__ __forceinline__ void reduce_finish(double v[NRED], SysState* S, int rb, int rnb)
+// Block reduction of NR partial sums; thread 0 stores the block's partial at slot rb.
+template <int NR>
+__device__ __forceinline__ void write_partials(double v[NRED], SysState* S, int rb)
 {
     __shared__ double lds[NRED * (BLOCK / 64)];
-    __shared__ int amlast;
-    if constexpr (NR > 0) block_sum<NR>(v, lds);
+    block_sum<NR>(v, lds);
     if (threadIdx.x == 0) {
-        if constexpr (NR > 0) {
 #pragma unroll
-            for (int k = 0; k < NR; k++) S->partials[(long)rb * NRED + k] = v[k];
-        }
-        __threadfence();
-        unsigned t = atomicAdd(&S->counter, 1u);
-        amlast = (t == (unsigned)(rnb - 1));
+        for (int k = 0; k < NR; k++) S->partials[(long)rb * NRED + k] = v[k];
     }
-    __syncthreads();
-    if (!amlast) return;
-    __threadfence();
+}
+
+// One block per system: fixed-order sum of the partials of the preceding kernel, then the
+// finisher. Gated launches skip systems that were not RUNNING (the preceding kernel skipped
+// them too, since only finishers change the status).
+template <int NR, int FIN>
+__global__ __launch_bounds__(BLOCK) void k_finish(const FinJob* __restrict__ fin, SysState* __restrict__ sys,
+                                                  int gated)
+{
+    __shared__ double lds[NRED * (BLOCK / 64)];
+    const FinJob F = fin[blockIdx.x];
+    SysState* S = sys + F.sys;
+    if (gated && S->status != ST_RUNNING) return;
     double tot[NRED] = {0.0, 0.0, 0.0, 0.0};
     if constexpr (NR > 0) {
-        double acc[NRED] = {0.0, 0.0, 0.0, 0.0};
-        for (int i = threadIdx.x; i < rnb; i += BLOCK) {
+        for (int i = threadIdx.x; i < F.rnblk; i += BLOCK) {
 #pragma unroll
-            for (int k = 0; k < NR; k++) acc[k] += __builtin_nontemporal_load(&S->partials[(long)i * NRED + k]);
+            for (int k = 0; k < NR; k++) tot[k] += S->partials[(long)i * NRED + k];
         }
-        __syncthreads();
-        block_sum<NR>(acc, lds);
-        if (threadIdx.x == 0)
-            for (int k = 0; k < NR; k++) tot[k] = acc[k];
+        block_sum<NR>(tot, lds);
     }
-    if (threadIdx.x == 0) {
-        finish<FIN>(S, tot);
-        atomicExch(&S->counter, 0u);
-    }
+    if (threadIdx.x == 0) finish<FIN>(S, tot);
 }
 
 // job of block b: jobs are sorted by blk0
@@ -223,30 +248,51 @@ __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int 
     }
 }
 
+template <int SF> struct HopGroup { static constexpr int G = WD_HOP_GROUP_LO; };
+template <> struct HopGroup<SF64> { static constexpr int G = WD_HOP_GROUP_64; };
+
+template <int D, int G>
+__device__ __forceinline__ void group_barrier()
+{
+    // after direction D (0..7): close the group
+    if constexpr (G < 8 && ((D + 1) % G) == 0 && D < 7) __builtin_amdgcn_sched_barrier(0);
+}
+
 template <bool DAG, int SFI, int LF, class T>
 __device__ __forceinline__ void hop_site(const Geo& g, int p, int cb, const SpinorRef& in, const void* links, long lcs,
                                          cx<T> acc[12])
 {
+    constexpr int G = HopGroup<SFI>::G;
     int x, y, z, t;
     cb_coords(g, p, cb, x, y, z, t);
 #pragma unroll
     for (int k = 0; k < 12; k++) acc[k] = mk<T>(T(0), T(0));
     hop_dir<0, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    group_barrier<0, G>();
     hop_dir<0, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    group_barrier<1, G>();
     hop_dir<1, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    group_barrier<2, G>();
     hop_dir<1, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    group_barrier<3, G>();
     hop_dir<2, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    group_barrier<4, G>();
     hop_dir<2, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    group_barrier<5, G>();
     hop_dir<3, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    group_barrier<6, G>();
     hop_dir<3, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
 }
 
+template <int SF> struct HopWaves { static constexpr int W = WD_HOP_WAVES_LO; };
+template <> struct HopWaves<SF64> { static constexpr int W = WD_HOP_WAVES_64; };
+
 template <int SF, int LF, bool DAG, int RED, int FIN>
-__global__ __launch_bounds__(BLOCK) void k_hop(const HopJob* __restrict__ jobs, int njobs, SysState* __restrict__ sys,
-                                               int gated)
+__global__ __launch_bounds__(BLOCK, HopWaves<SF>::W > 0 ? HopWaves<SF>::W : 1) void k_hop(
+    const HopJob* __restrict__ jobs, int njobs, SysState* __restrict__ sys, int gated)
 {
     using T = typename SReal<SF>::T;
-    const int b = blockIdx.x;
+    const int b = WD_XCD_REMAP ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
     const HopJob& J = jobs[find_job(jobs, njobs, b)];
     SysState* S = sys + J.sys;
     if (gated && S->status != ST_RUNNING) return;
@@ -294,10 +340,7 @@ __global__ __launch_bounds__(BLOCK) void k_hop(const HopJob* __restrict__ jobs, 
             for (int k = 0; k < 12; k++) v[2] += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
         }
     }
-    if constexpr (RED != RED_NONE || FIN != FIN_STORE) {
-        constexpr int NR = RED == RED_NONE ? 0 : 3;
-        reduce_finish<NR, FIN>(v, S, J.rblk0 + lb, J.rnblk);
-    }
+    if constexpr (RED != RED_NONE) write_partials<3>(v, S, J.rblk0 + lb);
 }
 
 // ================================================================ sweeps
@@ -359,7 +402,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
                 v[2] += (double)w[k].re * w[k].re + (double)w[k].im * w[k].im;
             }
         }
-        reduce_finish<3, FIN_ALPHA>(v, S, J.rblk0 + lb, J.rnblk);
+        write_partials<3>(v, S, J.rblk0 + lb);
     } else if constexpr (OP == OP_S) {
         // s <- r_{n+1} + alpha (s - chi A s)
         if (ok) {
@@ -372,7 +415,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
             for (int k = 0; k < 12; k++) s[k] = r[k] + alpha * (s[k] - chi * as[k]);
             store_spinor<SFL, T>(J.f[R_F0], i, s);
         }
-        reduce_finish<0, FIN_END>(v, S, J.rblk0 + lb, J.rnblk);
+
     } else if constexpr (OP == OP_SHIFT) {
         // BiCGstab-M: base s update, then every active shifted system
         //   x^s <- x^s - beta^s s^s + chi^s rho_n zeta_{n+1} w
@@ -411,7 +454,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
                 store_spinor<SFL, T>(sr, i, ss);
             }
         }
-        reduce_finish<0, FIN_END>(v, S, J.rblk0 + lb, J.rnblk);
+
     } else if constexpr (OP == OP_INIT) {
         // r_lo = r_hi; optionally rhat = r_lo, s = r_lo, x_lo = 0; then <rhat, r_lo>, |r_lo|^2
         if (ok) {
@@ -447,7 +490,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
                 v[2] += (double)r[k].re * r[k].re + (double)r[k].im * r[k].im;
             }
         }
-        reduce_finish<3, FIN_RESTART>(v, S, J.rblk0 + lb, J.rnblk);
+        write_partials<3>(v, S, J.rblk0 + lb);
     } else if constexpr (OP == OP_ACC) {
         // x_hi += x_lo  (flags & 1: then x_lo = 0)
         if (ok) {
@@ -472,7 +515,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
 #pragma unroll
             for (int k = 0; k < 12; k++) v[2] += a[k].re * a[k].re + a[k].im * a[k].im;
         }
-        reduce_finish<3, FIN_STORE>(v, S, J.rblk0 + lb, J.rnblk);
+        write_partials<3>(v, S, J.rblk0 + lb);
     } else if constexpr (OP == OP_MSINIT) {
         // BiCGstab-M start: r = s = rhat = b, x = 0, x^sigma = 0, s^sigma = b; |b|^2
         if (ok) {
@@ -495,7 +538,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
                 v[2] += n2;
             }
         }
-        reduce_finish<3, FIN_RESTART>(v, S, J.rblk0 + lb, J.rnblk);
+        write_partials<3>(v, S, J.rblk0 + lb);
     }
 }
 
@@ -719,6 +762,24 @@ static inline dim3 grid1(long nblk) { return dim3((unsigned)nblk); }
     HOP_CASE(SF_, LF_, DAG_, RED_NORM, FIN_STORE)                                                                  \
     HOP_CASE(SF_, LF_, DAG_, RED_ZDOT, FIN_BETA)                                                                   \
     HOP_CASE(SF_, LF_, DAG_, RED_OUTX, FIN_CHI)
+
+#define FIN_CASE(NR_, FIN_)                                                                                        \
+    if (nr == NR_ && fin == FIN_) {                                                                                \
+        hipLaunchKernelGGL((k_finish<NR_, FIN_>), dim3(nfin), dim3(BLOCK), 0, s, fins, sys, gated);               \
+        return hipGetLastError();                                                                                  \
+    }
+
+hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState* sys, int gated, hipStream_t s)
+{
+    if (nfin <= 0) return hipSuccess;
+    FIN_CASE(3, FIN_STORE)
+    FIN_CASE(3, FIN_BETA)
+    FIN_CASE(3, FIN_CHI)
+    FIN_CASE(3, FIN_ALPHA)
+    FIN_CASE(3, FIN_RESTART)
+    FIN_CASE(0, FIN_END)
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
                       SysState* sys, int gated, hipStream_t s)

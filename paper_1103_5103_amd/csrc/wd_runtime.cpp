@@ -107,10 +107,19 @@ void Timer::flush()
 template <class J>
 void JobTable<J>::upload(hipStream_t s)
 {
-    size_t n = host.size() * sizeof(J);
+    // finisher list: the systems of this launch in order of first appearance
+    fin.clear();
+    for (auto& j : host) {
+        bool seen = false;
+        for (auto& f : fin) seen = seen || f.sys == j.sys;
+        if (!seen) fin.push_back(FinJob{j.sys, j.rnblk});
+    }
+    const size_t off = fin_offset();
+    size_t n = off + fin.size() * sizeof(FinJob);
     if (!dev || dev->bytes < n) dev = std::make_shared<DevMem>(std::max(n, sizeof(J)));
-    void* stage = pinned(n);
-    std::memcpy(stage, host.data(), n);
+    char* stage = (char*)pinned(n);
+    std::memcpy(stage, host.data(), host.size() * sizeof(J));
+    std::memcpy(stage + off, fin.data(), fin.size() * sizeof(FinJob));
     WD_CHECK_HIP(hipMemcpyAsync(dev->p, stage, n, hipMemcpyHostToDevice, s));
     // the staging buffer is reused by the next upload: wait for this copy
     WD_CHECK_HIP(hipStreamSynchronize(s));
@@ -119,6 +128,23 @@ void JobTable<J>::upload(hipStream_t s)
 }
 template struct JobTable<HopJob>;
 template struct JobTable<SweepJob>;
+
+template <class J>
+static void run_finish(int nr, int fin, const JobTable<J>& t, SysState* sys, int gated, hipStream_t s)
+{
+    Timer& T = timer();
+    hipEvent_t a = nullptr, b = nullptr;
+    if (T.on) {
+        a = T.get();
+        b = T.get();
+        WD_CHECK_HIP(hipEventRecord(a, s));
+    }
+    WD_CHECK_HIP(launch_finish(nr, fin, t.fin_d(), (int)t.fin.size(), sys, gated, s));
+    if (T.on) {
+        WD_CHECK_HIP(hipEventRecord(b, s));
+        T.pending.push_back({TK_FINISH, a, b, 0.0});
+    }
+}
 
 void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>& t, SysState* sys, int gated,
              hipStream_t s, double bytes)
@@ -136,6 +162,7 @@ void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>&
         WD_CHECK_HIP(hipEventRecord(b, s));
         T.pending.push_back({cls, a, b, bytes});
     }
+    if (red != RED_NONE) run_finish(3, fin, t, sys, gated, s);
 }
 
 void run_sweep(int op, int sfl, const JobTable<SweepJob>& t, SysState* sys, int gated, hipStream_t s, double bytes)
@@ -151,6 +178,15 @@ void run_sweep(int op, int sfl, const JobTable<SweepJob>& t, SysState* sys, int 
     if (T.on) {
         WD_CHECK_HIP(hipEventRecord(b, s));
         T.pending.push_back({TK_SWEEP, a, b, bytes});
+    }
+    switch (op) {
+    case OP_XR: run_finish(3, FIN_ALPHA, t, sys, gated, s); break;
+    case OP_S:
+    case OP_SHIFT: run_finish(0, FIN_END, t, sys, gated, s); break;
+    case OP_INIT:
+    case OP_MSINIT: run_finish(3, FIN_RESTART, t, sys, gated, s); break;
+    case OP_NORM: run_finish(3, FIN_STORE, t, sys, gated, s); break;
+    default: break;
     }
 }
 

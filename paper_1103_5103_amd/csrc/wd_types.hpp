@@ -6,10 +6,11 @@
 // full-lattice operator is simply two jobs, one per output parity.
 //
 // Solver scalars live on the device (SysState), one record per system. Reductions are
-// deterministic: every block writes one partial sum, and the last block to finish (found with
-// an atomic ticket) adds the partials in a fixed order and then updates the scalars
-// ("finisher"). Kernels launched with gating skip systems whose status is not RUNNING, so a
-// whole chunk of iterations can be queued without host round trips.
+// deterministic: every block of a kernel writes one partial sum, and a small follow-up kernel
+// (one block per system) adds the partials in a fixed order and then updates the scalars
+// ("finisher"). The kernel boundary orders the two, so no device-wide fence is needed inside
+// the bandwidth-bound kernels. Kernels launched with gating skip systems whose status is not
+// RUNNING, so a whole chunk of iterations can be queued without host round trips.
 #pragma once
 #include "wd_device.hpp"
 
@@ -46,7 +47,6 @@ struct ShiftScal {
 };
 
 struct SysState {
-    unsigned counter;  // last-block ticket
     int status;        // SysStatus
     int pending;       // status committed at the end of the iteration
     int iter;
@@ -54,6 +54,7 @@ struct SysState {
     int mixed;
     int rsel;          // which residual buffer holds r_n (multi-shift keeps r_n and r_{n+1})
     int nshift;
+    int pad;
     double2 delta, beta, chi, alpha, beta_prev;
     double rr;         // |r|^2 of the iterated residual
     double maxrr;      // max |r|^2 since the last reliable update
@@ -64,6 +65,12 @@ struct SysState {
     double* partials;  // [max blocks][NRED]
     ShiftScal* sh;     // [nshift]
     SpinorRef* shv;    // [2 * nshift]: x_sigma, s_sigma
+};
+
+// one entry per system of a launch: which partial sums the finisher adds
+struct FinJob {
+    int sys;
+    int rnblk;
 };
 
 struct HopJob {
