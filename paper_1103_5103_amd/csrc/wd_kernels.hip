@@ -24,10 +24,10 @@
 // Directions whose loads may be scheduled together in the hop (8: all, 1: one at a time). A
 // scheduling barrier between groups bounds the live registers instead of spilling.
 #ifndef WD_HOP_GROUP_LO
-#define WD_HOP_GROUP_LO 8
+#define WD_HOP_GROUP_LO 4
 #endif
 #ifndef WD_HOP_GROUP_64
-#define WD_HOP_GROUP_64 8
+#define WD_HOP_GROUP_64 2
 #endif
 
 namespace wd {
@@ -203,14 +203,14 @@ template <> struct Proj<3> { static constexpr int E = 0, F = 0, I1 = 1, I2 = 0; 
 
 template <int MU, int D, bool DAG, int SFI, int LF, class T>
 __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int z, int t, const SpinorRef& in,
-                                        const void* links, long lcs, cx<T> acc[12])
+                                        const void* links, long lcs, cx<T> acc[12], int dep)
 {
     int xx = x, yy = y, zz = z, tt = t;
     if constexpr (MU == 0) xx = D == 0 ? (x + 1 == g.X ? 0 : x + 1) : (x == 0 ? g.X - 1 : x - 1);
     if constexpr (MU == 1) yy = D == 0 ? (y + 1 == g.Y ? 0 : y + 1) : (y == 0 ? g.Y - 1 : y - 1);
     if constexpr (MU == 2) zz = D == 0 ? (z + 1 == g.Z ? 0 : z + 1) : (z == 0 ? g.Z - 1 : z - 1);
     if constexpr (MU == 3) tt = D == 0 ? (t + 1 == g.T ? 0 : t + 1) : (t == 0 ? g.T - 1 : t - 1);
-    const int nb = cb_index(g, xx, yy, zz, tt);
+    const int nb = cb_index(g, xx, yy, zz, tt) + dep;
 
     cx<T> psi[12];
     load_spinor<SFI, T>(in, nb, psi);
@@ -225,7 +225,7 @@ __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int 
         h2[c] = psi[c * 4 + 2] + mul_ik<-F>(psi[c * 4 + I2]);
     }
     cx<T> W[9];
-    load_link<LF, T>(links, lcs, D == 0 ? MU : 4 + MU, cb, W);
+    load_link<LF, T>(links, lcs, D == 0 ? MU : 4 + MU, cb + dep, W);
     cx<T> g1[3], g2[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
@@ -251,11 +251,25 @@ __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int 
 template <int SF> struct HopGroup { static constexpr int G = WD_HOP_GROUP_LO; };
 template <> struct HopGroup<SF64> { static constexpr int G = WD_HOP_GROUP_64; };
 
-template <int D, int G>
-__device__ __forceinline__ void group_barrier()
+// Between groups of directions: an empty asm that reads every accumulator and then "writes"
+// the zero offset used by the next group's addresses. The volatile asms keep their order, so
+// the next group's loads cannot be issued before this group's results exist, which bounds the
+// number of live load registers (the FP64 hop otherwise spills).
+template <class T>
+__device__ __forceinline__ void order_after(cx<T> acc[12], int& dep)
+{
+#pragma unroll
+    for (int k = 0; k < 12; k += 3)
+        asm volatile("" ::"v"(acc[k].re), "v"(acc[k].im), "v"(acc[k + 1].re), "v"(acc[k + 1].im), "v"(acc[k + 2].re),
+                     "v"(acc[k + 2].im));
+    asm volatile("" : "+v"(dep));
+}
+
+template <int D, int G, class T>
+__device__ __forceinline__ void group_barrier(cx<T> acc[12], int& dep)
 {
     // after direction D (0..7): close the group
-    if constexpr (G < 8 && ((D + 1) % G) == 0 && D < 7) __builtin_amdgcn_sched_barrier(0);
+    if constexpr (G < 8 && ((D + 1) % G) == 0 && D < 7) order_after(acc, dep);
 }
 
 template <bool DAG, int SFI, int LF, class T>
@@ -267,21 +281,22 @@ __device__ __forceinline__ void hop_site(const Geo& g, int p, int cb, const Spin
     cb_coords(g, p, cb, x, y, z, t);
 #pragma unroll
     for (int k = 0; k < 12; k++) acc[k] = mk<T>(T(0), T(0));
-    hop_dir<0, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
-    group_barrier<0, G>();
-    hop_dir<0, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
-    group_barrier<1, G>();
-    hop_dir<1, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
-    group_barrier<2, G>();
-    hop_dir<1, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
-    group_barrier<3, G>();
-    hop_dir<2, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
-    group_barrier<4, G>();
-    hop_dir<2, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
-    group_barrier<5, G>();
-    hop_dir<3, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
-    group_barrier<6, G>();
-    hop_dir<3, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc);
+    int dep = 0;
+    hop_dir<0, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    group_barrier<0, G>(acc, dep);
+    hop_dir<0, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    group_barrier<1, G>(acc, dep);
+    hop_dir<1, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    group_barrier<2, G>(acc, dep);
+    hop_dir<1, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    group_barrier<3, G>(acc, dep);
+    hop_dir<2, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    group_barrier<4, G>(acc, dep);
+    hop_dir<2, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    group_barrier<5, G>(acc, dep);
+    hop_dir<3, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    group_barrier<6, G>(acc, dep);
+    hop_dir<3, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
 }
 
 template <int SF> struct HopWaves { static constexpr int W = WD_HOP_WAVES_LO; };
@@ -516,6 +531,33 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
             for (int k = 0; k < 12; k++) v[2] += a[k].re * a[k].re + a[k].im * a[k].im;
         }
         write_partials<3>(v, S, J.rblk0 + lb);
+    } else if constexpr (OP == OP_AXPY) {
+        // f0 = c0 f1 + f2 (FP64)
+        if (ok) {
+            cx<double> a[12], bq[12];
+            load_spinor<SF64, double>(J.f[R_F1], i, a);
+            load_spinor<SF64, double>(J.f[R_F2], i, bq);
+#pragma unroll
+            for (int k = 0; k < 12; k++) a[k] = J.c[0] * a[k] + bq[k];
+            store_spinor<SF64, double>(J.f[R_F0], i, a);
+        }
+    } else if constexpr (OP == OP_LINCOMB) {
+        // f0 (+)= sum_{j < m} c_j f_{1+j}, m = flags >> 8 (<= 7); flags & 1: accumulate into f0
+        if (ok) {
+            cx<double> acc[12], a[12];
+            if (J.flags & 1) load_spinor<SF64, double>(J.f[R_F0], i, acc);
+            else {
+#pragma unroll
+                for (int k = 0; k < 12; k++) acc[k] = mk<double>(0.0, 0.0);
+            }
+            const int m = J.flags >> 8;
+            for (int j = 0; j < m; j++) {
+                load_spinor<SF64, double>(J.f[1 + j], i, a);
+#pragma unroll
+                for (int k = 0; k < 12; k++) acc[k] = acc[k] + J.c[j] * a[k];
+            }
+            store_spinor<SF64, double>(J.f[R_F0], i, acc);
+        }
     } else if constexpr (OP == OP_MSINIT) {
         // BiCGstab-M start: r = s = rhat = b, x = 0, x^sigma = 0, s^sigma = b; |b|^2
         if (ok) {
@@ -816,6 +858,8 @@ hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long n
     SWEEP_CASE(OP_SHIFT, SF64)
     SWEEP_CASE(OP_NORM, SF64)
     SWEEP_CASE(OP_MSINIT, SF64)
+    SWEEP_CASE(OP_AXPY, SF64)
+    SWEEP_CASE(OP_LINCOMB, SF64)
     return hipErrorInvalidValue;
 }
 

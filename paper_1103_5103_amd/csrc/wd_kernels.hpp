@@ -5,7 +5,8 @@
 namespace wd {
 
 enum HopRed { RED_NONE = 0, RED_ZDOT = 1, RED_OUTX = 2, RED_NORM = 3 };
-enum SweepOp { OP_W = 0, OP_XR = 1, OP_S = 2, OP_SHIFT = 3, OP_INIT = 4, OP_ACC = 5, OP_NORM = 6, OP_MSINIT = 7 };
+enum SweepOp { OP_W = 0, OP_XR = 1, OP_S = 2, OP_SHIFT = 3, OP_INIT = 4, OP_ACC = 5, OP_NORM = 6, OP_MSINIT = 7, OP_AXPY = 8,
+               OP_LINCOMB = 9 };
 
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
                       SysState* sys, int gated, hipStream_t s);

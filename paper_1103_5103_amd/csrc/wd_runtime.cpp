@@ -104,6 +104,30 @@ void Timer::flush()
     pending.clear();
 }
 
+// Pinned staging for job tables: chunks are handed out in order and the arena is recycled only
+// after the device has drained (one device synchronisation per wrap-around), so uploads do not
+// wait for the stream.
+static char* stage_alloc(size_t n)
+{
+    static std::mutex mu;
+    static char* buf = nullptr;
+    static size_t cap = 0, off = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    n = (n + 255) / 256 * 256;
+    if (!buf) {
+        cap = (size_t)32 << 20;
+        WD_CHECK_HIP(hipHostMalloc((void**)&buf, cap, hipHostMallocDefault));
+    }
+    if (n > cap) throw Error{WD_ERR_ARG, "job table too large"};
+    if (off + n > cap) {
+        WD_CHECK_HIP(hipDeviceSynchronize());
+        off = 0;
+    }
+    char* p = buf + off;
+    off += n;
+    return p;
+}
+
 template <class J>
 void JobTable<J>::upload(hipStream_t s)
 {
@@ -117,12 +141,10 @@ void JobTable<J>::upload(hipStream_t s)
     const size_t off = fin_offset();
     size_t n = off + fin.size() * sizeof(FinJob);
     if (!dev || dev->bytes < n) dev = std::make_shared<DevMem>(std::max(n, sizeof(J)));
-    char* stage = (char*)pinned(n);
+    char* stage = stage_alloc(n);
     std::memcpy(stage, host.data(), host.size() * sizeof(J));
     std::memcpy(stage + off, fin.data(), fin.size() * sizeof(FinJob));
     WD_CHECK_HIP(hipMemcpyAsync(dev->p, stage, n, hipMemcpyHostToDevice, s));
-    // the staging buffer is reused by the next upload: wait for this copy
-    WD_CHECK_HIP(hipStreamSynchronize(s));
     nblocks = 0;
     for (auto& j : host) nblocks = std::max<long>(nblocks, (long)j.blk0 + j.nblk);
 }

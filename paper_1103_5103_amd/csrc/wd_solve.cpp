@@ -117,22 +117,41 @@ static double sweep_bytes(const JobTable<SweepJob>& t, double per_site)
 
 // ================================================================ even-odd BiCGstab (batched)
 
+// A packed source: b in the internal layout, h = 1/2 D_eo b_o (independent of the mass, so a
+// multi-mass solve computes it once) and |b|^2.
+struct EoSource {
+    Field B64, HB;
+    double bb = -1;
+};
+
 struct EoSys {
     wd_gauge* g;
     double kappa, a;
     const double* b;
     double* x;
     int slot;
-    Field B64, X64, BP, RH, T64, R64;
+    EoSource src;      // prepared by the caller, or built here
+    Field X64;         // FP64 solution (even half iterated, odd half rebuilt); caller-provided or own
+    bool x_ready = false;  // X64 already holds the start vector (use_x0 handled by the caller)
+    Field BP, RH, T64;
     Field r, rh, s, w, As, Aw, tmp, xl;
-    double bb = 0;
     bool done = false;
     int restarts = 0, reliable = 0;
     int final_status = WD_OK;
     int iters = 0;
+    double rr_true = -1;   // |r_prec|^2 of the last FP64 residual
     double true_rel = 0;
     double t0 = 0, t1 = 0;
 };
+
+static void prepare_source(wd_gauge* g, const std::string& key, const double* b, int dagger, EoSource& src,
+                           hipStream_t st)
+{
+    src.B64 = g->field(key + "B64", SF64, 2);
+    src.HB = g->field(key + "HB", SF64, 1);
+    WD_CHECK_HIP(launch_pack_spinor(SF64, b, g->geo, src.B64.half(0), src.B64.half(1), dagger, 1.0, st));
+    src.bb = -1;
+}
 
 static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream_t st, int poll)
 {
@@ -145,9 +164,8 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     for (auto& e : S) {
         e.g->ensure_links(LFL, st);
         const std::string k = "eo" + std::to_string(e.slot) + ".";
-        e.B64 = e.g->field(k + "B64", SF64, 2);
-        e.X64 = e.g->field(k + "X64", SF64, 2);
-        e.R64 = e.g->field(k + "R64", SF64, 2);
+        if (!e.src.B64.mem) prepare_source(e.g, k, e.b, P.dagger, e.src, st);
+        if (!e.X64.mem) e.X64 = e.g->field(k + "X64", SF64, 2);
         e.BP = e.g->field(k + "BP", SF64, 1);
         e.RH = e.g->field(k + "RH", SF64, 1);
         e.T64 = e.g->field(k + "T64", SF64, 1);
@@ -178,118 +196,78 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     }
     sys.upload(st);
 
-    // ---- setup: pack b (and x0), b_prec, |b|^2
-    for (auto& e : S) {
-        WD_CHECK_HIP(launch_pack_spinor(SF64, e.b, e.g->geo, e.B64.half(0), e.B64.half(1), P.dagger, 1.0, st));
-        if (P.use_x0)
-            WD_CHECK_HIP(launch_pack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st));
-        else
-            WD_CHECK_HIP(hipMemsetAsync(e.X64.base(), 0, e.X64.mem->bytes, st));
-    }
-    JobTable<HopJob> Hbp, Hx1, Hx2, Hrec, Hres;
-    JobTable<SweepJob> Nb, Init, Acc;
+    // ---- static job tables
+    JobTable<HopJob> Hhb, Hx1, Hx2, Hrec;
+    JobTable<SweepJob> Nb, Bp, InitFirst, InitRel, InitRestart, Acc;
+    JobTable<HopJob> H1, H2, H3, H4;
+    JobTable<SweepJob> SW, SXR, SS;
+    std::vector<int> need_src;
     for (int i = 0; i < n; i++) {
         EoSys& e = S[i];
         const Geo& g = e.g->geo;
-        // b_prec = a b_e + 1/2 D_eo b_o
-        HopJob j = hop_job(g, 0, i, e.B64.half(1), e.BP.all(), e.g->lk(L64_18, 0), e.g->lcs(), 0.5);
-        j.x0 = e.B64.half(0);
-        j.c0 = e.a;
-        Hbp.host.push_back(j);
-        // FP64 residual r_hi = b_prec - M_prec x_hi: T64 = D_oe x_e ; RH = b_prec - a^2 x_e + 1/4 D_eo T64
-        Hx1.host.push_back(hop_job(g, 1, i, e.X64.half(0), e.T64.all(), e.g->lk(L64_18, 1), e.g->lcs(), 1.0));
-        j = hop_job(g, 0, i, e.T64.all(), e.RH.all(), e.g->lk(L64_18, 0), e.g->lcs(), 0.25);
+        const void* d0 = e.g->lk(L64_18, 0);
+        const void* d1 = e.g->lk(L64_18, 1);
+        const long lcs = e.g->lcs();
+        if (e.src.bb < 0) {
+            need_src.push_back(i);
+            // h = 1/2 D_eo b_o ; |b|^2
+            Hhb.host.push_back(hop_job(g, 0, i, e.src.B64.half(1), e.src.HB.all(), d0, lcs, 0.5));
+            SweepJob nj = sweep_job(i, e.src.B64.nsites());
+            nj.f[R_F0] = e.src.B64.all();
+            Nb.host.push_back(nj);
+        }
+        // b_prec = a b_e + 1/2 D_eo b_o  (eq. eo4)
+        SweepJob bj = sweep_job(i, e.BP.nsites());
+        bj.f[R_F0] = e.BP.all();
+        bj.f[R_F1] = e.src.B64.half(0);
+        bj.f[R_F2] = e.src.HB.all();
+        bj.c[0] = e.a;
+        Bp.host.push_back(bj);
+        // FP64 residual r_hi = b_prec - M_prec x_e: T64 = D_oe x_e ; RH = b_prec - a^2 x_e + 1/4 D_eo T64
+        Hx1.host.push_back(hop_job(g, 1, i, e.X64.half(0), e.T64.all(), d1, lcs, 1.0));
+        HopJob j = hop_job(g, 0, i, e.T64.all(), e.RH.all(), d0, lcs, 0.25);
         j.x0 = e.BP.all();
         j.c0 = 1.0;
         j.x1 = e.X64.half(0);
         j.c1 = -e.a * e.a;
         Hx2.host.push_back(j);
-        // odd half: x_o = (b_o + 1/2 D_oe x_e) / a
-        j = hop_job(g, 1, i, e.X64.half(0), e.X64.half(1), e.g->lk(L64_18, 1), e.g->lcs(), 0.5 / e.a);
-        j.x0 = e.B64.half(1);
+        // odd half: x_o = (b_o + 1/2 D_oe x_e) / a  (eq. eo3)
+        j = hop_job(g, 1, i, e.X64.half(0), e.X64.half(1), d1, lcs, 0.5 / e.a);
+        j.x0 = e.src.B64.half(1);
         j.c0 = 1.0 / e.a;
         Hrec.host.push_back(j);
-        // true residual of the full system: R = b - a x + 1/2 D x, both parities
-        for (int p = 0; p < 2; p++) {
-            j = hop_job(g, p, i, e.X64.half(1 - p), e.R64.half(p), e.g->lk(L64_18, p), e.g->lcs(), 0.5);
-            j.x0 = e.B64.half(p);
-            j.c0 = 1.0;
-            j.x1 = e.X64.half(p);
-            j.c1 = -e.a;
-            Hres.host.push_back(j);
-        }
-        SweepJob sj = sweep_job(i, e.B64.nsites());
-        sj.f[R_F0] = e.B64.all();
-        Nb.host.push_back(sj);
-        sj = sweep_job(i, e.r.nsites());
+        SweepJob sj = sweep_job(i, e.r.nsites());
         sj.f[R_F0] = e.r.all();
         sj.f[R_F1] = e.RH.all();
         sj.f[R_F2] = e.rh.all();
         sj.f[R_F3] = e.s.all();
         sj.f[R_F4] = e.xl.all();
         sj.flags = 1 | 2 | 4;
-        Init.host.push_back(sj);
+        InitFirst.host.push_back(sj);
+        sj.flags = 0;
+        InitRel.host.push_back(sj);
+        sj.flags = 1 | 2;
+        InitRestart.host.push_back(sj);
         sj = sweep_job(i, e.xl.nsites());
         sj.f[R_F0] = e.X64.half(0);
         sj.f[R_F1] = e.xl.all();
         sj.flags = 1;
         Acc.host.push_back(sj);
-    }
-    for (auto* t : {&Hbp, &Hx1, &Hx2, &Hrec, &Hres}) {
-        layout(*t);
-        t->upload(st);
-    }
-    for (auto* t : {&Nb, &Init, &Acc}) {
-        layout(*t);
-        t->upload(st);
-    }
-    run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, Hbp, sys.d(), 0, st, hop_bytes(Hbp, SF64, L64_18, 1));
-    run_sweep(OP_NORM, SF64, Nb, sys.d(), 0, st, sweep_bytes(Nb, 192));
-    sys.download(st);
-    for (int i = 0; i < n; i++) {
-        S[i].bb = sys.h[i].red[2];
-        // |b_prec - M_prec x_e| < tol (1/(2 kappa)) |b| is |b - M x| < tol |b| (odd residual vanishes)
-        sys.h[i].target2 = P.tol * P.tol * S[i].a * S[i].a * S[i].bb;
-        if (S[i].bb == 0.0) {  // zero source: x = 0
-            S[i].done = true;
-            sys.h[i].status = ST_CONVERGED;
-        }
-    }
-    sys.upload(st);
-    if (P.use_x0) {
-        run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, Hx1, sys.d(), 0, st, hop_bytes(Hx1, SF64, L64_18, 0));
-        run_hop(SF64, L64_18, false, RED_NORM, FIN_STORE, Hx2, sys.d(), 0, st, hop_bytes(Hx2, SF64, L64_18, 2));
-    } else {
-        for (auto& j : Init.host) j.f[R_F1] = S[j.sys].BP.all();
-        Init.upload(st);
-    }
-    run_sweep(OP_INIT, SFL, Init, sys.d(), 1, st, 0);
-    if (!P.use_x0) {
-        for (auto& j : Init.host) j.f[R_F1] = S[j.sys].RH.all();
-        Init.upload(st);
-    }
-    for (int i = 0; i < n; i++) S[i].t0 = t_start;
-
-    // ---- iteration tables
-    JobTable<HopJob> H1, H2, H3, H4;
-    JobTable<SweepJob> SW, SXR, SS;
-    for (int i = 0; i < n; i++) {
-        EoSys& e = S[i];
-        const Geo& g = e.g->geo;
+        // iteration: As = a^2 s - 1/4 D_eo D_oe s, <rhat, As>; w; Aw = M_prec w, <Aw, w>, |Aw|^2; x, r; s
         const void* l0 = e.g->lk(LFL, 0);
         const void* l1 = e.g->lk(LFL, 1);
-        H1.host.push_back(hop_job(g, 1, i, e.s.all(), e.tmp.all(), l1, e.g->lcs(), 1.0));
-        HopJob j = hop_job(g, 0, i, e.tmp.all(), e.As.all(), l0, e.g->lcs(), -0.25);
+        H1.host.push_back(hop_job(g, 1, i, e.s.all(), e.tmp.all(), l1, lcs, 1.0));
+        j = hop_job(g, 0, i, e.tmp.all(), e.As.all(), l0, lcs, -0.25);
         j.x0 = e.s.all();
         j.c0 = e.a * e.a;
         j.z = e.rh.all();
         H2.host.push_back(j);
-        H3.host.push_back(hop_job(g, 1, i, e.w.all(), e.tmp.all(), l1, e.g->lcs(), 1.0));
-        j = hop_job(g, 0, i, e.tmp.all(), e.Aw.all(), l0, e.g->lcs(), -0.25);
+        H3.host.push_back(hop_job(g, 1, i, e.w.all(), e.tmp.all(), l1, lcs, 1.0));
+        j = hop_job(g, 0, i, e.tmp.all(), e.Aw.all(), l0, lcs, -0.25);
         j.x0 = e.w.all();
         j.c0 = e.a * e.a;
         H4.host.push_back(j);
-        SweepJob sj = sweep_job(i, e.r.nsites());
+        sj = sweep_job(i, e.r.nsites());
         sj.f[R_F0] = e.w.all();
         sj.f[R_F1] = e.r.all();
         sj.f[R_F2] = e.As.all();
@@ -311,14 +289,58 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         sj.f[R_F3] = e.r.all();
         SS.host.push_back(sj);
     }
-    for (auto* t : {&H1, &H2, &H3, &H4}) {
+    for (auto* t : {&Hhb, &Hx1, &Hx2, &Hrec, &H1, &H2, &H3, &H4}) {
         layout(*t);
-        t->upload(st);
+        if (!t->host.empty()) t->upload(st);
     }
-    for (auto* t : {&SW, &SXR, &SS}) {
+    for (auto* t : {&Nb, &Bp, &InitFirst, &InitRel, &InitRestart, &Acc, &SW, &SXR, &SS}) {
         layout(*t);
-        t->upload(st);
+        if (!t->host.empty()) t->upload(st);
     }
+
+    // ---- setup
+    if (!need_src.empty()) {
+        run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, Hhb, sys.d(), 0, st, hop_bytes(Hhb, SF64, L64_18, 0));
+        run_sweep(OP_NORM, SF64, Nb, sys.d(), 0, st, sweep_bytes(Nb, 192));
+        sys.download(st);
+        for (int i : need_src) S[i].src.bb = sys.h[i].red[2];
+    }
+    bool any_x0 = false;
+    for (auto& e : S) {
+        any_x0 = any_x0 || e.x_ready || P.use_x0;
+        if (e.x_ready) continue;
+        if (P.use_x0)
+            WD_CHECK_HIP(launch_pack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st));
+        else
+            WD_CHECK_HIP(hipMemsetAsync(e.X64.base(), 0, e.X64.mem->bytes, st));
+    }
+    run_sweep(OP_AXPY, SF64, Bp, sys.d(), 0, st, sweep_bytes(Bp, 3 * 192));
+    if (any_x0) {
+        // start vector: r_hi = b_prec - M_prec x0 (systems without one have x0 = 0 and get b_prec)
+        run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, Hx1, sys.d(), 0, st, hop_bytes(Hx1, SF64, L64_18, 0));
+        run_hop(SF64, L64_18, false, RED_NORM, FIN_STORE, Hx2, sys.d(), 0, st, hop_bytes(Hx2, SF64, L64_18, 2));
+    }
+    sys.download(st);
+    for (int i = 0; i < n; i++) {
+        EoSys& e = S[i];
+        if (any_x0) e.rr_true = sys.h[i].red[2];
+        // |b_prec - M_prec x_e| < tol (1/(2 kappa)) |b| is |b - M x| < tol |b| (the odd residual vanishes)
+        sys.h[i].target2 = P.tol * P.tol * e.a * e.a * e.src.bb;
+        sys.h[i].status = ST_RUNNING;
+        if (e.src.bb == 0.0) {  // zero source: x = 0
+            e.done = true;
+            e.rr_true = 0;
+            sys.h[i].status = ST_CONVERGED;
+        }
+    }
+    sys.upload(st);
+    if (!any_x0) {
+        for (auto& j : InitFirst.host) j.f[R_F1] = S[j.sys].BP.all();
+        InitFirst.upload(st);
+    }
+    run_sweep(OP_INIT, SFL, InitFirst, sys.d(), 1, st, 0);
+    for (int i = 0; i < n; i++) S[i].t0 = t_start;
+
     const double bl = spinor_site_bytes(SFL), bx = spinor_site_bytes(SFX);
     const double bH1 = hop_bytes(H1, SFL, LFL, 0), bH2 = hop_bytes(H2, SFL, LFL, 2), bH4 = hop_bytes(H4, SFL, LFL, 1);
     const double bSW = sweep_bytes(SW, 3 * bl), bSXR = sweep_bytes(SXR, 2 * bx + 5 * bl), bSS = sweep_bytes(SS, 4 * bl);
@@ -332,25 +354,29 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         run_sweep(OP_XR, SFL, SXR, sys.d(), 1, st, bSXR);
         run_sweep(OP_S, SFL, SS, sys.d(), 1, st, bSS);
     };
-
+    // tables restricted to a subset of the systems (the full tables when the subset is all)
+    auto subset = [&](const auto& full, const std::vector<int>& ids) {
+        std::remove_const_t<std::remove_reference_t<decltype(full)>> t;
+        for (int i : ids) t.host.push_back(full.host[i]);
+        layout(t);
+        t.upload(st);
+        return t;
+    };
     // reliable update for a subset: x_hi += x_lo, r_hi = b_prec - M_prec x_hi, |r_hi|^2
     auto reliable_update = [&](const std::vector<int>& ids) {
-        JobTable<SweepJob> A;
-        JobTable<HopJob> X1, X2;
-        for (int i : ids) {
-            A.host.push_back(Acc.host[i]);
-            X1.host.push_back(Hx1.host[i]);
-            X2.host.push_back(Hx2.host[i]);
+        if ((int)ids.size() == n) {
+            run_sweep(OP_ACC, SFL, Acc, sys.d(), 0, st, sweep_bytes(Acc, 2 * 192 + 2 * bx));
+            run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, Hx1, sys.d(), 0, st, hop_bytes(Hx1, SF64, L64_18, 0));
+            run_hop(SF64, L64_18, false, RED_NORM, FIN_STORE, Hx2, sys.d(), 0, st, hop_bytes(Hx2, SF64, L64_18, 2));
+            return;
         }
-        layout(A);
-        layout(X1);
-        layout(X2);
-        A.upload(st);
-        X1.upload(st);
-        X2.upload(st);
+        auto A = subset(Acc, ids);
+        auto X1 = subset(Hx1, ids);
+        auto X2 = subset(Hx2, ids);
         run_sweep(OP_ACC, SFL, A, sys.d(), 0, st, sweep_bytes(A, 2 * 192 + 2 * bx));
         run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, X1, sys.d(), 0, st, hop_bytes(X1, SF64, L64_18, 0));
         run_hop(SF64, L64_18, false, RED_NORM, FIN_STORE, X2, sys.d(), 0, st, hop_bytes(X2, SF64, L64_18, 2));
+        WD_CHECK_HIP(hipStreamSynchronize(st));  // the subset tables are released on return
     };
 
     int active = 0;
@@ -394,6 +420,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
             SysState& q = sys.h[i];
             e.reliable++;
             const double rr = q.red[2];
+            e.rr_true = rr;
             const int stt = q.status;
             if (!std::isfinite(rr)) {
                 e.done = true;
@@ -420,24 +447,25 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
             }
         }
         // new residual: keep rhat and s (reliable update) or restart with rhat = s = r (breakdown)
-        for (int pass = 0; pass < 2; pass++) {
-            const std::vector<int>& ids = pass == 0 ? cont : restart;
-            if (ids.empty()) continue;
-            JobTable<SweepJob> I;
-            for (int i : ids) {
-                SweepJob j = Init.host[i];
-                j.flags = pass == 0 ? 0 : (1 | 2);
-                I.host.push_back(j);
+        if (!cont.empty()) {
+            if ((int)cont.size() == n) run_sweep(OP_INIT, SFL, InitRel, sys.d(), 0, st, 0);
+            else {
+                auto I = subset(InitRel, cont);
+                run_sweep(OP_INIT, SFL, I, sys.d(), 0, st, 0);
+                WD_CHECK_HIP(hipStreamSynchronize(st));
             }
-            layout(I);
-            I.upload(st);
+        }
+        if (!restart.empty()) {
+            auto I = subset(InitRestart, restart);
             run_sweep(OP_INIT, SFL, I, sys.d(), 0, st, 0);
+            WD_CHECK_HIP(hipStreamSynchronize(st));
         }
     }
 
-    // ---- finish: odd half, FP64 true residual of the full system, unpack
+    // ---- finish: odd half from eq. eo3, unpack. With x_o from eq. eo3 the full residual is
+    // b - M x = (b_prec - M_prec x_e) / a on the even sites and exactly zero on the odd ones, so
+    // the last FP64 residual gives the true relative residual without another operator pass.
     run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, Hrec, sys.d(), 0, st, hop_bytes(Hrec, SF64, L64_18, 1));
-    run_hop(SF64, L64_18, false, RED_NORM, FIN_STORE, Hres, sys.d(), 0, st, hop_bytes(Hres, SF64, L64_18, 2));
     for (auto& e : S)
         WD_CHECK_HIP(launch_unpack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st));
     sys.download(st);
@@ -445,7 +473,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         EoSys& e = S[i];
         if (e.t1 == 0) e.t1 = now_s();
         e.iters = sys.h[i].iter;
-        e.true_rel = e.bb > 0 ? std::sqrt(sys.h[i].red[2] / e.bb) : 0.0;
+        e.true_rel = (e.src.bb > 0 && e.rr_true >= 0) ? std::sqrt(e.rr_true) / (e.a * std::sqrt(e.src.bb)) : 0.0;
     }
 }
 
@@ -724,6 +752,7 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
                           int guess, const wd_solver_params& P, wd_solver_stats* stats, hipStream_t st)
 {
     WD_REQUIRE(n >= 1 && n <= 32, "number of masses must be in 1..32");
+    for (int i = 0; i < n; i++) WD_REQUIRE(kappas[i] > 0, "kappa must be positive");
     if (method == WD_METHOD_MULTISHIFT) return solve_multishift(g, n, kappas, x, b, P, stats, st);
     WD_REQUIRE(method == WD_METHOD_SEQUENTIAL, "unknown method");
     WD_REQUIRE(guess == WD_GUESS_NONE || guess == WD_GUESS_POLY, "unknown guess");
@@ -731,20 +760,39 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
     for (int i = 0; i < n; i++) order[i] = i;
     // heaviest mass (smallest kappa) first (Sec. 7)
     std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return kappas[p] < kappas[q]; });
-    double** d_ptrs = (double**)g->rawbuf("mm.ptrs", sizeof(double*) * 64);
-    double* d_coef = (double*)g->rawbuf("mm.coef", sizeof(double) * 64);
-    std::vector<int> done;
     wd_status worst = WD_OK;
-    const long ncomplex = g->V * 12;
+    if (!P.eo) {
+        if (guess != WD_GUESS_NONE) throw Error{WD_ERR_UNSUPPORTED, "start guesses need even-odd preconditioning"};
+        for (int idx : order) {
+            wd_status s = solve_single(g, kappas[idx], x[idx], b, P, stats ? &stats[idx] : nullptr, st);
+            if (s != WD_OK && worst == WD_OK) worst = s;
+        }
+        return worst;
+    }
+    // the source is packed once and 1/2 D_eo b_o is shared by all masses; every mass keeps its
+    // FP64 solution so that the next start vector is a combination of them in the internal layout
+    EoSource src;
+    prepare_source(g, "mm.", b, P.dagger, src, st);
+    std::vector<Field> X(n);
+    for (int i = 0; i < n; i++) X[i] = g->field("mm.X" + std::to_string(i), SF64, 2);
+    SysState* dummy = (SysState*)g->rawbuf("apply.sys", sizeof(SysState));
+    std::vector<int> done;
     for (int idx : order) {
         wd_solver_params Q = P;
         Q.use_x0 = 0;
+        EoSys e;
+        e.g = g;
+        e.kappa = kappas[idx];
+        e.b = b;
+        e.x = x[idx];
+        e.slot = 0;
+        e.src = src;
+        e.X64 = X[idx];
         if (guess == WD_GUESS_POLY && !done.empty()) {
             // Lagrange weights in m a = 1/(2 kappa) - 4 (Sec. 6.2.1), highest order available
             const double m = 1.0 / (2.0 * kappas[idx]) - 4.0;
             const int k = (int)done.size();
             std::vector<double> c(k);
-            std::vector<const double*> ptr(k);
             for (int jj = 0; jj < k; jj++) {
                 const double mj = 1.0 / (2.0 * kappas[done[jj]]) - 4.0;
                 double w = 1.0;
@@ -754,19 +802,37 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
                     w *= (m - mi) / (mj - mi);
                 }
                 c[jj] = w;
-                ptr[jj] = x[done[jj]];
             }
-            char* stg = (char*)pinned(64 * 16);
-            std::memcpy(stg, ptr.data(), sizeof(double*) * k);
-            std::memcpy(stg + 512, c.data(), sizeof(double) * k);
-            WD_CHECK_HIP(hipMemcpyAsync(d_ptrs, stg, sizeof(double*) * k, hipMemcpyHostToDevice, st));
-            WD_CHECK_HIP(hipMemcpyAsync(d_coef, stg + 512, sizeof(double) * k, hipMemcpyHostToDevice, st));
-            WD_CHECK_HIP(launch_lincomb(x[idx], (const double* const*)d_ptrs, d_coef, k, ncomplex, st));
-            WD_CHECK_HIP(hipStreamSynchronize(st));
-            Q.use_x0 = 1;
+            // x0_e = sum_j c_j x_j,e  in chunks of 7 inputs per sweep
+            for (int j0 = 0; j0 < k; j0 += 7) {
+                JobTable<SweepJob> L;
+                SweepJob sj = sweep_job(0, X[idx].stride);
+                sj.f[R_F0] = X[idx].half(0);
+                const int m7 = std::min(7, k - j0);
+                for (int jj = 0; jj < m7; jj++) {
+                    sj.f[1 + jj] = X[done[j0 + jj]].half(0);
+                    sj.c[jj] = c[j0 + jj];
+                }
+                sj.flags = (m7 << 8) | (j0 > 0 ? 1 : 0);
+                L.host.push_back(sj);
+                layout(L);
+                L.upload(st);
+                run_sweep(OP_LINCOMB, SF64, L, dummy, 0, st, sweep_bytes(L, (m7 + 1 + (j0 > 0)) * 192.0));
+                WD_CHECK_HIP(hipStreamSynchronize(st));
+            }
+            e.x_ready = true;
         }
-        wd_status s = solve_single(g, kappas[idx], x[idx], b, Q, stats ? &stats[idx] : nullptr, st);
-        if (s != WD_OK && worst == WD_OK) worst = s;
+        std::vector<EoSys> S{e};
+        eo_solve(S, Q, st, 4);
+        src = S[0].src;  // |b|^2 is known after the first mass
+        if (stats) {
+            stats[idx].iters = S[0].iters;
+            stats[idx].reliable_updates = S[0].reliable;
+            stats[idx].status = S[0].final_status;
+            stats[idx].true_rel_res = S[0].true_rel;
+            stats[idx].seconds = S[0].t1 - S[0].t0;
+        }
+        if (S[0].final_status != WD_OK && worst == WD_OK) worst = (wd_status)S[0].final_status;
         done.push_back(idx);
     }
     return worst;

@@ -102,6 +102,7 @@ struct SweepJob {
     int rnblk;
     int flags;   // op-specific
     int pad;
+    double c[8]; // op-specific coefficients
     SpinorRef f[NROLE];
 };
 
