@@ -171,6 +171,21 @@ __device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const c
     }
 }
 
+// ---------------------------------------------------------------- streaming loads
+// Links are read exactly once per hop: non-temporal loads keep them from evicting the neighbour
+// spinors that other sites of the same XCD are about to re-read from L2.
+#ifndef WD_NT_LINKS
+#define WD_NT_LINKS 1
+#endif
+template <class V>
+__device__ __forceinline__ V ld_stream(const V* p)
+{
+    if constexpr (WD_NT_LINKS) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
 // ---------------------------------------------------------------- links
 __device__ __forceinline__ float bf16_to_f32(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
 // round to nearest even; inputs are finite link entries
@@ -181,49 +196,83 @@ __device__ __forceinline__ unsigned short f32_to_bf16(float f)
     return (unsigned short)(u >> 16);
 }
 
-// Load link slot k of output site i into W[3][3]. base: link array of this output parity,
-// chunk j of slot k at base[(k * nchunks + j) * lcs + i].
+// 16-bit link formats pair the forward and backward link of one direction: chunk j (0..2) of pair
+// mu is 16 bytes, the first 8 from slot mu (forward) and the last 8 from slot 4 + mu (backward),
+// so a hop reads both links of a direction with three 16-byte loads.
+__host__ __device__ constexpr bool link_paired(int f) { return f == L16_12 || f == LB16_12; }
+
+template <class T>
+__device__ __forceinline__ void recon_row2(cx<T> W[9])
+{
+    // row 2 = conj(row0 x row1)
+    W[6] = cconj(W[1] * W[5] - W[2] * W[4]);
+    W[7] = cconj(W[2] * W[3] - W[0] * W[5]);
+    W[8] = cconj(W[0] * W[4] - W[1] * W[3]);
+}
+
+template <int LF, class T>
+__device__ __forceinline__ void unpack16(unsigned short a, unsigned short b, cx<T>& z)
+{
+    if constexpr (LF == L16_12) {
+        z = mk<T>((T)(float)__builtin_bit_cast(_Float16, a), (T)(float)__builtin_bit_cast(_Float16, b));
+    } else {
+        z = mk<T>((T)bf16_to_f32(a), (T)bf16_to_f32(b));
+    }
+}
+
+// Load link slot k (0..3 forward U_mu(n), 4..7 backward U_mu(n-mu)^dag) of output site i into
+// W[3][3]. Unpaired formats: chunk j of slot k at base[(k * nchunks + j) * lcs + i].
 template <int LF, class T>
 __device__ __forceinline__ void load_link(const void* base, long lcs, int k, long i, cx<T> W[9])
 {
     if constexpr (LF == L64_18 || LF == L64_12) {
         constexpr int nc = link_chunks(LF);
-        const double2* p = (const double2*)base + (long)k * nc * lcs + i;
+        const d2v* p = (const d2v*)base + (long)k * nc * lcs + i;
 #pragma unroll
         for (int j = 0; j < nc; j++) {
-            double2 q = p[j * lcs];
-            W[j] = mk<T>((T)q.x, (T)q.y);
+            d2v q = ld_stream(p + j * lcs);
+            W[j] = mk<T>((T)q[0], (T)q[1]);
         }
     } else if constexpr (LF == L32_12) {
-        const float4* p = (const float4*)base + (long)k * 3 * lcs + i;
+        const f4v* p = (const f4v*)base + (long)k * 3 * lcs + i;
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            float4 q = p[j * lcs];
-            W[2 * j] = mk<T>((T)q.x, (T)q.y);
-            W[2 * j + 1] = mk<T>((T)q.z, (T)q.w);
+            f4v q = ld_stream(p + j * lcs);
+            W[2 * j] = mk<T>((T)q[0], (T)q[1]);
+            W[2 * j + 1] = mk<T>((T)q[2], (T)q[3]);
         }
-    } else if constexpr (LF == L16_12) {
-        const h4* p = (const h4*)base + (long)k * 3 * lcs + i;
+    } else if constexpr (link_paired(LF)) {
+        const u16x4* p = (const u16x4*)base + 2 * ((long)(k & 3) * 3 * lcs + i) + (k >> 2);
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            h4 q = p[j * lcs];
-            W[2 * j] = mk<T>((T)(float)q[0], (T)(float)q[1]);
-            W[2 * j + 1] = mk<T>((T)(float)q[2], (T)(float)q[3]);
-        }
-    } else if constexpr (LF == LB16_12) {
-        const u16x4* p = (const u16x4*)base + (long)k * 3 * lcs + i;
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            u16x4 q = p[j * lcs];
-            W[2 * j] = mk<T>((T)bf16_to_f32(q[0]), (T)bf16_to_f32(q[1]));
-            W[2 * j + 1] = mk<T>((T)bf16_to_f32(q[2]), (T)bf16_to_f32(q[3]));
+            u16x4 q = ld_stream(p + 2 * j * lcs);
+            unpack16<LF, T>(q[0], q[1], W[2 * j]);
+            unpack16<LF, T>(q[2], q[3], W[2 * j + 1]);
         }
     }
-    if constexpr (link_recon12(LF)) {
-        // row 2 = conj(row0 x row1)
-        W[6] = cconj(W[1] * W[5] - W[2] * W[4]);
-        W[7] = cconj(W[2] * W[3] - W[0] * W[5]);
-        W[8] = cconj(W[0] * W[4] - W[1] * W[3]);
+    if constexpr (link_recon12(LF)) recon_row2(W);
+}
+
+// Both links of direction mu: forward U_mu(n) into Wf, backward U_mu(n-mu)^dag into Wb.
+template <int LF, class T>
+__device__ __forceinline__ void load_link_pair(const void* base, long lcs, int mu, long i, cx<T> Wf[9], cx<T> Wb[9])
+{
+    if constexpr (link_paired(LF)) {
+        typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+        const u16x8* p = (const u16x8*)base + (long)mu * 3 * lcs + i;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            u16x8 q = ld_stream(p + j * lcs);
+            unpack16<LF, T>(q[0], q[1], Wf[2 * j]);
+            unpack16<LF, T>(q[2], q[3], Wf[2 * j + 1]);
+            unpack16<LF, T>(q[4], q[5], Wb[2 * j]);
+            unpack16<LF, T>(q[6], q[7], Wb[2 * j + 1]);
+        }
+        recon_row2(Wf);
+        recon_row2(Wb);
+    } else {
+        load_link<LF, T>(base, lcs, mu, i, Wf);
+        load_link<LF, T>(base, lcs, 4 + mu, i, Wb);
     }
 }
 
@@ -242,7 +291,7 @@ __device__ __forceinline__ void store_link(void* base, long lcs, int k, long i, 
             p[j * lcs] = make_float4((float)W[2 * j].re, (float)W[2 * j].im, (float)W[2 * j + 1].re,
                                      (float)W[2 * j + 1].im);
     } else if constexpr (LF == L16_12) {
-        h4* p = (h4*)base + (long)k * 3 * lcs + i;
+        h4* p = (h4*)base + 2 * ((long)(k & 3) * 3 * lcs + i) + (k >> 2);
 #pragma unroll
         for (int j = 0; j < 3; j++) {
             h4 q;
@@ -250,10 +299,10 @@ __device__ __forceinline__ void store_link(void* base, long lcs, int k, long i, 
             q[1] = (_Float16)(float)W[2 * j].im;
             q[2] = (_Float16)(float)W[2 * j + 1].re;
             q[3] = (_Float16)(float)W[2 * j + 1].im;
-            p[j * lcs] = q;
+            p[2 * j * lcs] = q;
         }
     } else if constexpr (LF == LB16_12) {
-        u16x4* p = (u16x4*)base + (long)k * 3 * lcs + i;
+        u16x4* p = (u16x4*)base + 2 * ((long)(k & 3) * 3 * lcs + i) + (k >> 2);
 #pragma unroll
         for (int j = 0; j < 3; j++) {
             u16x4 q;
@@ -261,7 +310,7 @@ __device__ __forceinline__ void store_link(void* base, long lcs, int k, long i, 
             q[1] = f32_to_bf16((float)W[2 * j].im);
             q[2] = f32_to_bf16((float)W[2 * j + 1].re);
             q[3] = f32_to_bf16((float)W[2 * j + 1].im);
-            p[j * lcs] = q;
+            p[2 * j * lcs] = q;
         }
     }
 }

@@ -69,9 +69,12 @@ size_t field_bytes(int sf, int halves, long stride);
 enum { TK_HOP_LO = 0, TK_HOP_F64 = 1, TK_SWEEP = 2, TK_FINISH = 3, NTK = 4 };
 struct Timer {
     bool on = false;
-    struct Rec { int cls; hipEvent_t a, b; double bytes; };
+    struct Rec { int cls; hipEvent_t a, b; double bytes; int slot; };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
+    int* dflags = nullptr;  // per pending launch: set by the kernel when it did work
+    size_t cap = 0;
+    int* slot();
     double ms[NTK] = {0, 0, 0, 0};
     double bytes[NTK] = {0, 0, 0, 0};
     long launches[NTK] = {0, 0, 0, 0};

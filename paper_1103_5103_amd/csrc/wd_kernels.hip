@@ -24,7 +24,7 @@
 // Directions whose loads may be scheduled together in the hop (8: all, 1: one at a time). A
 // scheduling barrier between groups bounds the live registers instead of spilling.
 #ifndef WD_HOP_GROUP_LO
-#define WD_HOP_GROUP_LO 4
+#define WD_HOP_GROUP_LO 2
 #endif
 #ifndef WD_HOP_GROUP_64
 #define WD_HOP_GROUP_64 2
@@ -201,9 +201,9 @@ template <> struct Proj<1> { static constexpr int E = 2, F = 0, I1 = 0, I2 = 1; 
 template <> struct Proj<2> { static constexpr int E = 3, F = 1, I1 = 1, I2 = 0; };
 template <> struct Proj<3> { static constexpr int E = 0, F = 0, I1 = 1, I2 = 0; };
 
-template <int MU, int D, bool DAG, int SFI, int LF, class T>
+template <int MU, int D, bool DAG, int SFI, class T>
 __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int z, int t, const SpinorRef& in,
-                                        const void* links, long lcs, cx<T> acc[12], int dep)
+                                        const cx<T> W[9], cx<T> acc[12], int dep)
 {
     int xx = x, yy = y, zz = z, tt = t;
     if constexpr (MU == 0) xx = D == 0 ? (x + 1 == g.X ? 0 : x + 1) : (x == 0 ? g.X - 1 : x - 1);
@@ -224,8 +224,6 @@ __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int 
         h1[c] = psi[c * 4 + 3] + mul_ik<-E>(psi[c * 4 + I1]);
         h2[c] = psi[c * 4 + 2] + mul_ik<-F>(psi[c * 4 + I2]);
     }
-    cx<T> W[9];
-    load_link<LF, T>(links, lcs, D == 0 ? MU : 4 + MU, cb + dep, W);
     cx<T> g1[3], g2[3];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
@@ -272,6 +270,20 @@ __device__ __forceinline__ void group_barrier(cx<T> acc[12], int& dep)
     if constexpr (G < 8 && ((D + 1) % G) == 0 && D < 7) order_after(acc, dep);
 }
 
+// Both directions of axis MU; the two links are loaded together (one 16-byte load per chunk for
+// the paired 16-bit formats). G = directions per ordering group.
+template <int MU, int G, bool DAG, int SFI, int LF, class T>
+__device__ __forceinline__ void hop_axis(const Geo& g, int cb, int x, int y, int z, int t, const SpinorRef& in,
+                                         const void* links, long lcs, cx<T> acc[12], int& dep)
+{
+    cx<T> Wf[9], Wb[9];
+    load_link_pair<LF, T>(links, lcs, MU, cb + dep, Wf, Wb);
+    hop_dir<MU, 0, DAG, SFI, T>(g, cb, x, y, z, t, in, Wf, acc, dep);
+    group_barrier<2 * MU, G>(acc, dep);
+    hop_dir<MU, 1, DAG, SFI, T>(g, cb, x, y, z, t, in, Wb, acc, dep);
+    group_barrier<2 * MU + 1, G>(acc, dep);
+}
+
 template <bool DAG, int SFI, int LF, class T>
 __device__ __forceinline__ void hop_site(const Geo& g, int p, int cb, const SpinorRef& in, const void* links, long lcs,
                                          cx<T> acc[12])
@@ -282,29 +294,33 @@ __device__ __forceinline__ void hop_site(const Geo& g, int p, int cb, const Spin
 #pragma unroll
     for (int k = 0; k < 12; k++) acc[k] = mk<T>(T(0), T(0));
     int dep = 0;
-    hop_dir<0, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    group_barrier<0, G>(acc, dep);
-    hop_dir<0, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    group_barrier<1, G>(acc, dep);
-    hop_dir<1, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    group_barrier<2, G>(acc, dep);
-    hop_dir<1, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    group_barrier<3, G>(acc, dep);
-    hop_dir<2, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    group_barrier<4, G>(acc, dep);
-    hop_dir<2, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    group_barrier<5, G>(acc, dep);
-    hop_dir<3, 0, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    group_barrier<6, G>(acc, dep);
-    hop_dir<3, 1, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    hop_axis<0, G, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    hop_axis<1, G, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    hop_axis<2, G, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    hop_axis<3, G, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
 }
 
 template <int SF> struct HopWaves { static constexpr int W = WD_HOP_WAVES_LO; };
 template <> struct HopWaves<SF64> { static constexpr int W = WD_HOP_WAVES_64; };
 
+// Job-local block order. With tz > 0 the blocks walk t fastest inside groups of tz z-planes, so a
+// block's t +- 1 neighbours were (or are about to be) loaded by blocks running on the same XCD at
+// nearly the same time, while the site order would put them a whole t-slice apart.
+__device__ __forceinline__ int tiled_block(const HopJob& J, int lb)
+{
+    if (J.tz <= 0) return lb;
+    const int q = lb % J.bpp;
+    int r = lb / J.bpp;
+    const int zz = r % J.tz;
+    r /= J.tz;
+    const int t = r % J.g.T;
+    const int zg = r / J.g.T;
+    return q + J.bpp * ((zg * J.tz + zz) + J.g.Z * t);
+}
+
 template <int SF, int LF, bool DAG, int RED, int FIN>
 __global__ __launch_bounds__(BLOCK, HopWaves<SF>::W > 0 ? HopWaves<SF>::W : 1) void k_hop(
-    const HopJob* __restrict__ jobs, int njobs, SysState* __restrict__ sys, int gated)
+    const HopJob* __restrict__ jobs, int njobs, SysState* __restrict__ sys, int gated, int* exec)
 {
     using T = typename SReal<SF>::T;
     const int b = WD_XCD_REMAP ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
@@ -312,7 +328,8 @@ __global__ __launch_bounds__(BLOCK, HopWaves<SF>::W > 0 ? HopWaves<SF>::W : 1) v
     SysState* S = sys + J.sys;
     if (gated && S->status != ST_RUNNING) return;
     const int lb = b - J.blk0;
-    const int cb = lb * BLOCK + threadIdx.x;
+    if (exec && lb == 0 && threadIdx.x == 0) atomicOr(exec, 1);  // timing: this launch did work
+    const int cb = tiled_block(J, lb) * BLOCK + threadIdx.x;
     double v[NRED] = {0.0, 0.0, 0.0, 0.0};
     if (cb < J.g.Vh) {
         cx<T> acc[12];
@@ -364,7 +381,7 @@ template <class T> __device__ __forceinline__ cx<T> cvt(double2 a) { return mk<T
 
 template <int OP, int SFL>
 __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jobs, int njobs,
-                                                 SysState* __restrict__ sys, int gated)
+                                                 SysState* __restrict__ sys, int gated, int* exec)
 {
     using T = typename SReal<SFL>::T;
     constexpr int SFX = SFL == SF64 ? SF64 : SF32;  // storage of the low-precision solution
@@ -373,6 +390,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
     SysState* S = sys + J.sys;
     if (gated && S->status != ST_RUNNING) return;
     const int lb = b - J.blk0;
+    if (exec && lb == 0 && threadIdx.x == 0) atomicOr(exec, 1);
     const long i = (long)lb * BLOCK + threadIdx.x;
     const bool ok = i < J.n;
     double v[NRED] = {0.0, 0.0, 0.0, 0.0};
@@ -796,7 +814,7 @@ static inline dim3 grid1(long nblk) { return dim3((unsigned)nblk); }
 #define HOP_CASE(SF_, LF_, DAG_, RED_, FIN_)                                                                        \
     if (sf == SF_ && lf == LF_ && dag == DAG_ && red == RED_ && fin == FIN_) {                                     \
         hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs,    \
-                           sys, gated);                                                                           \
+                           sys, gated, exec);                                                                     \
         return hipGetLastError();                                                                                  \
     }
 #define HOP_REDS(SF_, LF_, DAG_)                                                                                   \
@@ -824,7 +842,7 @@ hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState
 }
 
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
-                      SysState* sys, int gated, hipStream_t s)
+                      SysState* sys, int gated, hipStream_t s, int* exec)
 {
     if (nblocks <= 0) return hipSuccess;
     HOP_REDS(SF64, L64_18, false)
@@ -841,7 +859,7 @@ hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* 
 
 #define SWEEP_CASE(OP_, SF_)                                                                                       \
     if (op == OP_ && sfl == SF_) {                                                                                 \
-        hipLaunchKernelGGL((k_sweep<OP_, SF_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs, sys, gated);       \
+        hipLaunchKernelGGL((k_sweep<OP_, SF_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs, sys, gated, exec); \
         return hipGetLastError();                                                                                  \
     }
 #define SWEEP_ALL(SF_)                                                                                             \
@@ -849,7 +867,7 @@ hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* 
     SWEEP_CASE(OP_XR, SF_) SWEEP_CASE(OP_S, SF_) SWEEP_CASE(OP_INIT, SF_) SWEEP_CASE(OP_ACC, SF_)
 
 hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long nblocks, SysState* sys, int gated,
-                        hipStream_t s)
+                        hipStream_t s, int* exec)
 {
     if (nblocks <= 0) return hipSuccess;
     SWEEP_ALL(SF64)

@@ -89,15 +89,37 @@ hipEvent_t Timer::get()
     WD_CHECK_HIP(hipEventCreate(&e));
     return e;
 }
+int* Timer::slot()
+{
+    if (!dflags) {
+        cap = 1 << 16;
+        WD_CHECK_HIP(hipMalloc(&dflags, cap * sizeof(int)));
+        WD_CHECK_HIP(hipMemset(dflags, 0, cap * sizeof(int)));
+    }
+    if (pending.size() >= cap) flush();
+    return dflags + pending.size();
+}
+
+// Launches that every system skipped (gated iterations after convergence) are not counted:
+// their kernels ran for a few microseconds and moved no data.
 void Timer::flush()
 {
-    for (auto& r : pending) {
-        WD_CHECK_HIP(hipEventSynchronize(r.b));
-        float t = 0;
-        WD_CHECK_HIP(hipEventElapsedTime(&t, r.a, r.b));
-        ms[r.cls] += t;
-        bytes[r.cls] += r.bytes;
-        launches[r.cls] += 1;
+    if (pending.empty()) return;
+    std::vector<int> done(pending.size(), 1);
+    WD_CHECK_HIP(hipDeviceSynchronize());
+    if (dflags) {
+        WD_CHECK_HIP(hipMemcpy(done.data(), dflags, done.size() * sizeof(int), hipMemcpyDeviceToHost));
+        WD_CHECK_HIP(hipMemset(dflags, 0, done.size() * sizeof(int)));
+    }
+    for (size_t k = 0; k < pending.size(); k++) {
+        Rec& r = pending[k];
+        if (r.slot < 0 || done[k]) {
+            float t = 0;
+            WD_CHECK_HIP(hipEventElapsedTime(&t, r.a, r.b));
+            ms[r.cls] += t;
+            bytes[r.cls] += r.bytes;
+            launches[r.cls] += 1;
+        }
         pool.push_back(r.a);
         pool.push_back(r.b);
     }
@@ -164,7 +186,7 @@ static void run_finish(int nr, int fin, const JobTable<J>& t, SysState* sys, int
     WD_CHECK_HIP(launch_finish(nr, fin, t.fin_d(), (int)t.fin.size(), sys, gated, s));
     if (T.on) {
         WD_CHECK_HIP(hipEventRecord(b, s));
-        T.pending.push_back({TK_FINISH, a, b, 0.0});
+        T.pending.push_back({TK_FINISH, a, b, 0.0, -1});
     }
 }
 
@@ -174,15 +196,17 @@ void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>&
     Timer& T = timer();
     hipEvent_t a = nullptr, b = nullptr;
     const int cls = sf == SF64 ? TK_HOP_F64 : TK_HOP_LO;
+    int* flag = nullptr;
     if (T.on) {
+        flag = T.slot();
         a = T.get();
         b = T.get();
         WD_CHECK_HIP(hipEventRecord(a, s));
     }
-    WD_CHECK_HIP(launch_hop(sf, lf, dag, red, fin, t.d(), t.n(), t.nblocks, sys, gated, s));
+    WD_CHECK_HIP(launch_hop(sf, lf, dag, red, fin, t.d(), t.n(), t.nblocks, sys, gated, s, flag));
     if (T.on) {
         WD_CHECK_HIP(hipEventRecord(b, s));
-        T.pending.push_back({cls, a, b, bytes});
+        T.pending.push_back({cls, a, b, bytes, (int)(flag - T.dflags)});
     }
     if (red != RED_NONE) run_finish(3, fin, t, sys, gated, s);
 }
@@ -191,15 +215,17 @@ void run_sweep(int op, int sfl, const JobTable<SweepJob>& t, SysState* sys, int 
 {
     Timer& T = timer();
     hipEvent_t a = nullptr, b = nullptr;
+    int* flag = nullptr;
     if (T.on) {
+        flag = T.slot();
         a = T.get();
         b = T.get();
         WD_CHECK_HIP(hipEventRecord(a, s));
     }
-    WD_CHECK_HIP(launch_sweep(op, sfl, t.d(), t.n(), t.nblocks, sys, gated, s));
+    WD_CHECK_HIP(launch_sweep(op, sfl, t.d(), t.n(), t.nblocks, sys, gated, s, flag));
     if (T.on) {
         WD_CHECK_HIP(hipEventRecord(b, s));
-        T.pending.push_back({TK_SWEEP, a, b, bytes});
+        T.pending.push_back({TK_SWEEP, a, b, bytes, (int)(flag - T.dflags)});
     }
     switch (op) {
     case OP_XR: run_finish(3, FIN_ALPHA, t, sys, gated, s); break;

@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "wd_host.hpp"
@@ -58,6 +60,86 @@ struct SysArray {
 };
 
 static inline int nblk(long n) { return (int)((n + BLOCK - 1) / BLOCK); }
+
+// ---------------------------------------------------------------- block-order autotuner
+// Candidate orders: site order (tz = 0) or t fastest within groups of tz z-planes. Each is timed
+// on the real lattice (one hop with the solver's storage formats); the fastest is kept per
+// (lattice extents, spinor format, link format) for the life of the process. WD_TILE=<tz>
+// overrides the choice.
+static std::map<std::string, int>& tile_cache()
+{
+    static std::map<std::string, int> c;
+    return c;
+}
+
+static bool tile_valid(const Geo& g, int tz)
+{
+    if (tz == 0) return true;
+    return tz > 0 && (g.Xh * g.Y) % BLOCK == 0 && g.Z % tz == 0 && g.Vh % BLOCK == 0;
+}
+
+static void set_tile(HopJob& j, int tz)
+{
+    if (!tile_valid(j.g, tz)) tz = 0;
+    j.tz = tz;
+    j.bpp = tz > 0 ? j.g.Xh * j.g.Y / BLOCK : 0;
+}
+
+static HopJob hop_job(const Geo& g, int parity, int sys, const SpinorRef& in, const SpinorRef& out,
+                      const void* links, long lcs, double c2);
+template <class J> static void layout(JobTable<J>& t);
+
+int tune_tile(wd_gauge* g, int sf, int lf, hipStream_t st)
+{
+    const Geo& G = g->geo;
+    if (const char* env = std::getenv("WD_TILE")) {
+        int tz = std::atoi(env);
+        return tile_valid(G, tz) ? tz : 0;
+    }
+    if ((G.Xh * G.Y) % BLOCK != 0 || G.Vh < (1 << 16)) return 0;
+    char key[96];
+    std::snprintf(key, sizeof(key), "%d.%d.%d.%d.%d.%d", G.X, G.Y, G.Z, G.T, sf, lf);
+    auto it = tile_cache().find(key);
+    if (it != tile_cache().end()) return it->second;
+    g->ensure_links(lf, st);
+    Field in = g->field("tune.in", sf, 1), out = g->field("tune.out", sf, 1);
+    SysState* dummy = (SysState*)g->rawbuf("apply.sys", sizeof(SysState));
+    hipEvent_t e0, e1;
+    WD_CHECK_HIP(hipEventCreate(&e0));
+    WD_CHECK_HIP(hipEventCreate(&e1));
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int tz : {0, 2, 4, 8, 16}) {
+        if (!tile_valid(G, tz)) continue;
+        JobTable<HopJob> t;
+        HopJob j = hop_job(G, 1, 0, in.all(), out.all(), g->lk(lf, 1), g->lcs(), 1.0);
+        set_tile(j, tz);
+        t.host.push_back(j);
+        layout(t);
+        t.upload(st);
+        for (int w = 0; w < 2; w++)
+            WD_CHECK_HIP(launch_hop(sf, lf, false, RED_NONE, FIN_STORE, t.d(), t.n(), t.nblocks, dummy, 0, st));
+        WD_CHECK_HIP(hipEventRecord(e0, st));
+        for (int w = 0; w < 6; w++)
+            WD_CHECK_HIP(launch_hop(sf, lf, false, RED_NONE, FIN_STORE, t.d(), t.n(), t.nblocks, dummy, 0, st));
+        WD_CHECK_HIP(hipEventRecord(e1, st));
+        WD_CHECK_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        WD_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = tz;
+        }
+    }
+    WD_CHECK_HIP(hipEventDestroy(e0));
+    WD_CHECK_HIP(hipEventDestroy(e1));
+    if (std::getenv("WD_VERBOSE"))
+        std::fprintf(stderr, "wdirac: block order for %s: tz=%d (%.1f us per hop)\n", key, best, best_ms * 1e3 / 6);
+    g->ws.erase("tune.in");
+    g->ws.erase("tune.out");
+    tile_cache()[key] = best;
+    return best;
+}
 
 static HopJob hop_job(const Geo& g, int parity, int sys, const SpinorRef& in, const SpinorRef& out,
                       const void* links, long lcs, double c2)
@@ -161,6 +243,11 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     const int LFL = P.mixed ? link_fmt_of(P.link_store, P.recon) : L64_18;
     const double t_start = now_s();
 
+    std::vector<int> tile_lo(n), tile_64(n);
+    for (int i = 0; i < n; i++) {
+        tile_lo[i] = tune_tile(S[i].g, SFL, LFL, st);
+        tile_64[i] = tune_tile(S[i].g, SF64, L64_18, st);
+    }
     for (auto& e : S) {
         e.g->ensure_links(LFL, st);
         const std::string k = "eo" + std::to_string(e.slot) + ".";
@@ -289,6 +376,10 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         sj.f[R_F3] = e.r.all();
         SS.host.push_back(sj);
     }
+    for (auto* t : {&Hhb, &Hx1, &Hx2, &Hrec})
+        for (auto& j : t->host) set_tile(j, tile_64[j.sys]);
+    for (auto* t : {&H1, &H2, &H3, &H4})
+        for (auto& j : t->host) set_tile(j, tile_lo[j.sys]);
     for (auto* t : {&Hhb, &Hx1, &Hx2, &Hrec, &H1, &H2, &H3, &H4}) {
         layout(*t);
         if (!t->host.empty()) t->upload(st);
@@ -592,7 +683,9 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
         layout(*t);
         t->upload(st);
     }
+    const int tz64 = tune_tile(g, SF64, L64_18, st);
     for (auto* t : {&HAs, &HAw}) {
+        for (auto& h : t->host) set_tile(h, tz64);
         layout(*t);
         t->upload(st);
     }
@@ -663,6 +756,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
             h.c0 = 1.0;
             h.x1 = Xi.half(p);
             h.c1 = -ai;
+            set_tile(h, tz64);
             R.host.push_back(h);
         }
         layout(R);

@@ -88,6 +88,8 @@ struct HopJob {
     const void* links;   // the 8 links per site of this output parity
     long lcs;            // link chunk stride
     double c0, c1, c2;   // out = c0 x0 + c1 x1 + c2 * hop
+    int tz;              // block order: 0 = site order; > 0 = t fastest within groups of tz z-planes
+    int bpp;             // blocks per (z, t) plane when tz > 0
 };
 
 // Roles of the fields of a sweep job
