@@ -41,6 +41,8 @@ __host__ __device__ constexpr int link_chunk_bytes(int f)
     return (f == L64_18 || f == L64_12 || f == L32_12) ? 16 : 8;
 }
 __host__ __device__ constexpr bool link_recon12(int f) { return f != L64_18 && f != L32_18; }
+// 16-byte chunks per site holding all 8 links of that site
+__host__ __device__ constexpr int link_site_chunks(int f) { return 8 * link_chunks(f) * link_chunk_bytes(f) / 16; }
 
 // ---------------------------------------------------------------- complex
 template <class T>
@@ -98,6 +100,22 @@ __device__ __forceinline__ int cb_index(const Geo& g, int x, int y, int z, int t
     return (x >> 1) + g.Xh * (y + g.Y * (z + g.Z * t));
 }
 
+// ---------------------------------------------------------------- chunk addressing
+// WD_AOSOA = B > 0 stores fields and links in blocks of B sites with all chunks of a block
+// contiguous (chunk j of site i at ((i / B) * nchunks + j) * B + i % B), so one wavefront's loads
+// of a site quantity fall into one contiguous region. WD_AOSOA = 0 keeps one array per chunk
+// (chunk j of site i at j * cs + i).
+#ifndef WD_AOSOA
+#define WD_AOSOA 0
+#endif
+constexpr long AOSOA_B = WD_AOSOA;  // sites per block (a power of two dividing 256), 0: plain arrays
+constexpr bool AOSOA = AOSOA_B > 0;
+__host__ __device__ __forceinline__ long chunk_at(int nchunks, long cs, long i, int j)
+{
+    if constexpr (AOSOA) return ((i / AOSOA_B) * nchunks + j) * AOSOA_B + (i % AOSOA_B);
+    else return j * cs + i;
+}
+
 // ---------------------------------------------------------------- field views
 struct SpinorRef {
     void* p;     // chunk 0 of site 0 of this view
@@ -115,14 +133,14 @@ __device__ __forceinline__ void load_spinor(const SpinorRef& r, long i, cx<T> v[
         const double2* p = (const double2*)r.p;
 #pragma unroll
         for (int j = 0; j < 12; j++) {
-            double2 q = p[j * r.cs + i];
+            double2 q = p[chunk_at(12, r.cs, i, j)];
             v[j] = mk<T>((T)q.x, (T)q.y);
         }
     } else if constexpr (SF == SF32) {
         const float4* p = (const float4*)r.p;
 #pragma unroll
         for (int j = 0; j < 6; j++) {
-            float4 q = p[j * r.cs + i];
+            float4 q = p[chunk_at(6, r.cs, i, j)];
             v[2 * j] = mk<T>((T)q.x, (T)q.y);
             v[2 * j + 1] = mk<T>((T)q.z, (T)q.w);
         }
@@ -131,7 +149,7 @@ __device__ __forceinline__ void load_spinor(const SpinorRef& r, long i, cx<T> v[
         const float n = r.nrm[i];
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            h8 q = p[j * r.cs + i];
+            h8 q = p[chunk_at(3, r.cs, i, j)];
 #pragma unroll
             for (int k = 0; k < 4; k++) v[4 * j + k] = mk<T>((T)((float)q[2 * k] * n), (T)((float)q[2 * k + 1] * n));
         }
@@ -144,12 +162,12 @@ __device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const c
     if constexpr (SF == SF64) {
         double2* p = (double2*)r.p;
 #pragma unroll
-        for (int j = 0; j < 12; j++) p[j * r.cs + i] = make_double2((double)v[j].re, (double)v[j].im);
+        for (int j = 0; j < 12; j++) p[chunk_at(12, r.cs, i, j)] = make_double2((double)v[j].re, (double)v[j].im);
     } else if constexpr (SF == SF32) {
         float4* p = (float4*)r.p;
 #pragma unroll
         for (int j = 0; j < 6; j++)
-            p[j * r.cs + i] = make_float4((float)v[2 * j].re, (float)v[2 * j].im, (float)v[2 * j + 1].re,
+            p[chunk_at(6, r.cs, i, j)] = make_float4((float)v[2 * j].re, (float)v[2 * j].im, (float)v[2 * j + 1].re,
                                           (float)v[2 * j + 1].im);
     } else {
         h8* p = (h8*)r.p;
@@ -166,7 +184,7 @@ __device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const c
                 q[2 * k] = (_Float16)((float)v[4 * j + k].re * inv);
                 q[2 * k + 1] = (_Float16)((float)v[4 * j + k].im * inv);
             }
-            p[j * r.cs + i] = q;
+            p[chunk_at(3, r.cs, i, j)] = q;
         }
     }
 }
@@ -225,27 +243,28 @@ __device__ __forceinline__ void unpack16(unsigned short a, unsigned short b, cx<
 template <int LF, class T>
 __device__ __forceinline__ void load_link(const void* base, long lcs, int k, long i, cx<T> W[9])
 {
+    constexpr int NCT = link_site_chunks(LF);
     if constexpr (LF == L64_18 || LF == L64_12) {
         constexpr int nc = link_chunks(LF);
-        const d2v* p = (const d2v*)base + (long)k * nc * lcs + i;
+        const d2v* p = (const d2v*)base;
 #pragma unroll
         for (int j = 0; j < nc; j++) {
-            d2v q = ld_stream(p + j * lcs);
+            d2v q = ld_stream(p + chunk_at(NCT, lcs, i, k * nc + j));
             W[j] = mk<T>((T)q[0], (T)q[1]);
         }
     } else if constexpr (LF == L32_12) {
-        const f4v* p = (const f4v*)base + (long)k * 3 * lcs + i;
+        const f4v* p = (const f4v*)base;
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            f4v q = ld_stream(p + j * lcs);
+            f4v q = ld_stream(p + chunk_at(NCT, lcs, i, k * 3 + j));
             W[2 * j] = mk<T>((T)q[0], (T)q[1]);
             W[2 * j + 1] = mk<T>((T)q[2], (T)q[3]);
         }
     } else if constexpr (link_paired(LF)) {
-        const u16x4* p = (const u16x4*)base + 2 * ((long)(k & 3) * 3 * lcs + i) + (k >> 2);
+        const u16x4* p = (const u16x4*)base;
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            u16x4 q = ld_stream(p + 2 * j * lcs);
+            u16x4 q = ld_stream(p + 2 * chunk_at(NCT, lcs, i, (k & 3) * 3 + j) + (k >> 2));
             unpack16<LF, T>(q[0], q[1], W[2 * j]);
             unpack16<LF, T>(q[2], q[3], W[2 * j + 1]);
         }
@@ -259,10 +278,10 @@ __device__ __forceinline__ void load_link_pair(const void* base, long lcs, int m
 {
     if constexpr (link_paired(LF)) {
         typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
-        const u16x8* p = (const u16x8*)base + (long)mu * 3 * lcs + i;
+        const u16x8* p = (const u16x8*)base;
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            u16x8 q = ld_stream(p + j * lcs);
+            u16x8 q = ld_stream(p + chunk_at(12, lcs, i, mu * 3 + j));
             unpack16<LF, T>(q[0], q[1], Wf[2 * j]);
             unpack16<LF, T>(q[2], q[3], Wf[2 * j + 1]);
             unpack16<LF, T>(q[4], q[5], Wb[2 * j]);
@@ -279,38 +298,41 @@ __device__ __forceinline__ void load_link_pair(const void* base, long lcs, int m
 template <int LF>
 __device__ __forceinline__ void store_link(void* base, long lcs, int k, long i, const cx<double> W[9])
 {
+    constexpr int NCT = link_site_chunks(LF);
     if constexpr (LF == L64_18 || LF == L64_12) {
         constexpr int nc = link_chunks(LF);
-        double2* p = (double2*)base + (long)k * nc * lcs + i;
+        double2* p = (double2*)base;
 #pragma unroll
-        for (int j = 0; j < nc; j++) p[j * lcs] = make_double2(W[j].re, W[j].im);
+        for (int j = 0; j < nc; j++) p[chunk_at(NCT, lcs, i, k * nc + j)] = make_double2(W[j].re, W[j].im);
     } else if constexpr (LF == L32_12) {
-        float4* p = (float4*)base + (long)k * 3 * lcs + i;
+        float4* p = (float4*)base;
 #pragma unroll
         for (int j = 0; j < 3; j++)
-            p[j * lcs] = make_float4((float)W[2 * j].re, (float)W[2 * j].im, (float)W[2 * j + 1].re,
+            p[chunk_at(NCT, lcs, i, k * 3 + j)] = make_float4((float)W[2 * j].re, (float)W[2 * j].im, (float)W[2 * j + 1].re,
                                      (float)W[2 * j + 1].im);
     } else if constexpr (LF == L16_12) {
-        h4* p = (h4*)base + 2 * ((long)(k & 3) * 3 * lcs + i) + (k >> 2);
+        h4* p = (h4*)base;
 #pragma unroll
         for (int j = 0; j < 3; j++) {
+            h4* pj = p + 2 * chunk_at(NCT, lcs, i, (k & 3) * 3 + j) + (k >> 2);
             h4 q;
             q[0] = (_Float16)(float)W[2 * j].re;
             q[1] = (_Float16)(float)W[2 * j].im;
             q[2] = (_Float16)(float)W[2 * j + 1].re;
             q[3] = (_Float16)(float)W[2 * j + 1].im;
-            p[2 * j * lcs] = q;
+            *pj = q;
         }
     } else if constexpr (LF == LB16_12) {
-        u16x4* p = (u16x4*)base + 2 * ((long)(k & 3) * 3 * lcs + i) + (k >> 2);
+        u16x4* p = (u16x4*)base;
 #pragma unroll
         for (int j = 0; j < 3; j++) {
+            u16x4* pj = p + 2 * chunk_at(NCT, lcs, i, (k & 3) * 3 + j) + (k >> 2);
             u16x4 q;
             q[0] = f32_to_bf16((float)W[2 * j].re);
             q[1] = f32_to_bf16((float)W[2 * j].im);
             q[2] = f32_to_bf16((float)W[2 * j + 1].re);
             q[3] = f32_to_bf16((float)W[2 * j + 1].im);
-            p[2 * j * lcs] = q;
+            *pj = q;
         }
     }
 }

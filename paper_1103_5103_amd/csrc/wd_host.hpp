@@ -54,7 +54,7 @@ struct Field {
     SpinorRef half(int p) const
     {
         SpinorRef r;
-        r.p = base() + (size_t)p * stride * 16;
+        r.p = base() + (size_t)p * stride * 16 * (AOSOA ? spinor_chunks(sf) : 1);
         float* n = nrm();
         r.nrm = n ? n + (size_t)p * stride : nullptr;
         r.cs = cs();
