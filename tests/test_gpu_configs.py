@@ -1,0 +1,171 @@
+"""GPU parity at the real sizes of the benchmark configurations, through the C ABI.
+
+Full-size results are checked with the CPU oracle where it can afford it: one FP64 oracle
+operator application per checked mass gives the true residual |b - M x|/|b| (1e-8 for mixed
+precision), and the FP64 operator itself is compared element by element.
+"""
+import numpy as np
+import pytest
+import torch
+
+import lattice_inputs as li
+import oracle
+import paper_1103_5103_amd as wd
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def big():
+    """32^3x64, near-Haar links and the Gaussian source of the benchmark (same seeds)."""
+    dims = (32, 32, 32, 64)
+    _say("generating 32^3x64 inputs")
+    U = li.random_links(dims, 1.0, 1002)
+    b = li.gaussian_field(dims, 2002)
+    g = wd.wd_gauge_create(_t(U), hint=wd.params())
+    yield dims, U, b, g
+    g.close()
+
+
+def test_apply_full_size(big):
+    dims, U, b, g = big
+    out = _n(wd.wd_apply(g, 0.134, _t(b)))
+    ref = oracle.apply(U, 0.134, b)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 1e-14
+
+
+def test_mixed_solve_full_size_bench_config(big):
+    """The benchmark's sequential mixed solve (FP32 spinors, FP16 links, delta 1e-3, poly guess)
+    for the lightest and heaviest masses of the 8."""
+    dims, U, b, g = big
+    kappas = [0.120 + 0.002 * k for k in range(8)]
+    xs, sts = wd.wd_multimass_solve(g, kappas, _t(b), p=wd.params(tol=1e-8, spinor="f32", links="f16", delta=1e-3))
+    for i in (0, 7):
+        res = oracle.true_residual(U, kappas[i], _n(xs[i]), b)
+        _say("32^3x64 mixed", kappas[i], sts[i], "oracle residual", res)
+        assert res < 1e-8
+        assert abs(sts[i]["true_rel_res"] - res) < 1e-2 * res
+
+
+def test_multishift_full_size(big):
+    dims, U, b, g = big
+    kappas = [0.120 + 0.002 * k for k in range(8)]
+    xs, sts = wd.bicgstab_m_solve(g, kappas, _t(b), p=wd.params(tol=1e-8, mixed=False, eo=False))
+    for i in (0, 7):
+        res = oracle.true_residual(U, kappas[i], _n(xs[i]), b)
+        _say("32^3x64 BiCGstab-M", kappas[i], sts[i], "oracle residual", res)
+        assert res < 1e-8
+
+
+def test_multimass_16x32_fp64_vs_mixed():
+    """16^3x32, 6 masses: BiCGstab-M (FP64) and sequential even-odd mixed BiCGstab with FP16
+    spinors and links, both to 1e-8 for every mass."""
+    dims = (16, 16, 16, 32)
+    U = li.random_links(dims, 1.0, 1001)
+    b = li.gaussian_field(dims, 2001)
+    kappas = [0.120, 0.122, 0.124, 0.126, 0.128, 0.130]
+    g = wd.wd_gauge_create(_t(U))
+    bd = _t(b)
+    xm, stm = wd.bicgstab_m_solve(g, kappas, bd, p=wd.params(tol=1e-8, mixed=False, eo=False))
+    xs, sts = wd.wd_multimass_solve(g, kappas, bd, p=wd.params(tol=1e-8, spinor="f16", links="f16"))
+    for k, a, c in zip(kappas, xm, xs):
+        ra = oracle.true_residual(U, k, _n(a), b)
+        rc = oracle.true_residual(U, k, _n(c), b)
+        assert ra < 1e-8 and rc < 1e-8, (k, ra, rc)
+        # the two solutions agree within the condition number times the tolerance
+        assert np.linalg.norm(_n(a) - _n(c)) / np.linalg.norm(_n(a)) < 1e-6
+    g.close()
+
+
+def test_batched_full_config():
+    """12 spin-colour point sources x 4 masses on 16^3x32, plus 8^4, 12^4 and 16^4 lattices with
+    4 point sources x the same 4 masses each: 96 systems in one batched solve."""
+    kappas = [0.124, 0.126, 0.128, 0.130]
+    lattices = [((16, 16, 16, 32), 1100, 12), ((8, 8, 8, 8), 1101, 4), ((12, 12, 12, 12), 1102, 4),
+                ((16, 16, 16, 16), 1103, 4)]
+    systems, refs, gauges = [], [], []
+    for dims, seed, nsrc in lattices:
+        U = li.random_links(dims, 1.0, seed)
+        g = wd.wd_gauge_create(_t(U), hint=wd.params(spinor="f16", links="f16"))
+        gauges.append(g)
+        for s in range(nsrc):
+            b = li.point_source(dims, spin=s % 4, colour=s // 4)
+            bd = _t(b)
+            for k in kappas:
+                systems.append((g, k, bd, torch.zeros(g.field_shape, dtype=torch.complex128, device=DEV)))
+                refs.append((U, k, b))
+    _say("batched systems:", len(systems))
+    sts = wd.wd_batch_solve(systems, p=wd.params(tol=1e-8, spinor="f16", links="f16"))
+    worst = 0.0
+    for (g, k, bd, x), (U, kk, b), s in zip(systems, refs, sts):
+        assert s["status"] == 0, s
+        worst = max(worst, oracle.true_residual(U, kk, _n(x), b))
+    _say("batched worst oracle residual", worst)
+    assert worst < 1e-8
+    for g in gauges:
+        g.close()
+
+
+def test_gradient_finite_differences_8444():
+    """L = Re<eta, M(0.125)^{-1} b> on 8^4: the GPU gradient (autograd backward through the library)
+    against central differences h = 1e-6 along +h and +ih of 20 random link entries, with the
+    perturbed solves done by the CPU oracle."""
+    dims = (8, 8, 8, 8)
+    kappa = 0.125
+    U = li.random_links(dims, 1.0, 1050)
+    b = li.gaussian_field(dims, 2050)
+    eta = li.gaussian_field(dims, 2051)
+    Ud = _t(U).requires_grad_(True)
+    x = wd.wilson_solve(Ud, _t(b), kappa, params=wd.params(tol=1e-14, mixed=False, max_iter=500))
+    torch.real(torch.sum(torch.conj(_t(eta)) * x)).backward()
+    G = _n(Ud.grad).reshape(-1)
+
+    def loss(Uc):
+        xs, _, _, _ = oracle.bicgstab(Uc, kappa, b, tol=1e-15, maxit=1000, eo=True)
+        return float(np.real(np.vdot(eta, xs)))
+
+    rng = np.random.default_rng(7)
+    flat = U.reshape(-1)
+    h = 1e-6
+    for _ in range(20):
+        j = int(rng.integers(0, flat.size))
+        fd = []
+        for step in (h, 1j * h):
+            Up = flat.copy()
+            Up[j] += step
+            Um = flat.copy()
+            Um[j] -= step
+            fd.append((loss(Up.reshape(U.shape)) - loss(Um.reshape(U.shape))) / (2 * h))
+        d = fd[0] + 1j * fd[1]
+        assert abs(d - G[j]) < 1e-6 * max(1.0, abs(d)), (j, d, G[j])
+
+
+def test_gradient_mixed_16x32():
+    """Forward and backward in mixed precision on 16^3x32: grad_b solves the adjoint system to 1e-8."""
+    dims = (16, 16, 16, 32)
+    kappa = 0.125
+    U = li.random_links(dims, 1.0, 1060)
+    b = li.gaussian_field(dims, 2060)
+    eta = li.gaussian_field(dims, 2061)
+    Ud = _t(U).requires_grad_(True)
+    bd = _t(b).requires_grad_(True)
+    x = wd.wilson_solve(Ud, bd, kappa, params=wd.params(tol=1e-8))
+    torch.real(torch.sum(torch.conj(_t(eta)) * x)).backward()
+    lam = _n(bd.grad)
+    r = eta - oracle.apply(U, kappa, lam, dag=True)
+    assert np.linalg.norm(r) / np.linalg.norm(eta) < 1e-8
+    assert oracle.true_residual(U, kappa, _n(x), b) < 1e-8
+    assert np.isfinite(_n(Ud.grad)).all()
