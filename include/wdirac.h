@@ -94,7 +94,7 @@ typedef struct {
     double* x;         /* device, [V][3][4] complex128 solution     */
 } wd_system;
 
-enum { WD_METHOD_SEQUENTIAL = 0, WD_METHOD_MULTISHIFT = 1 };
+enum { WD_METHOD_SEQUENTIAL = 0, WD_METHOD_MULTISHIFT = 1, WD_METHOD_BATCHED = 2 };
 enum { WD_GUESS_NONE = 0, WD_GUESS_POLY = 1 };
 
 /* Defaults: tol 1e-8, max_iter 5000, mixed 1, F32 spinors, F16 links, recon 12, eo 1,
@@ -145,7 +145,9 @@ wd_status bicgstab_m_solve(wd_gauge* g, int n, const double* kappas, double* con
  * Multi-mass driver (Sec. 6, eq. 6.1; Sec. 7). method WD_METHOD_SEQUENTIAL: single-mass BiCGstab
  * once per mass, heaviest mass (smallest kappa) first; with WD_GUESS_POLY each start vector is the
  * highest-order Lagrange extrapolation in m a of the solutions found so far (Sec. 6.2.1).
- * method WD_METHOD_MULTISHIFT: one bicgstab_m_solve. 1 <= n <= 32.
+ * method WD_METHOD_MULTISHIFT: one bicgstab_m_solve. method WD_METHOD_BATCHED: the single-mass
+ * systems of all masses iterate together (one kernel launch per solver step for all of them,
+ * converged masses drop out, even-odd required); no start guesses. 1 <= n <= 32.
  */
 wd_status wd_multimass_solve(wd_gauge* g, int n, const double* kappas, double* const* x, const double* b,
                              int method, int guess, const wd_solver_params* params,
@@ -187,6 +189,13 @@ wd_status wd_last_error(char* buf, size_t n);
 void wd_timing_enable(int on);
 void wd_timing_reset(void);
 wd_status wd_timing_get(int kernel_class, double* total_ms, long* launches, double* bytes);
+
+/*
+ * Execution option: replay each chunk of solver iterations from a captured HIP graph (1) or launch
+ * its kernels one by one (0, the default: capturing per solve costs more than it saves here). Results are identical either way. Graphs are not used
+ * while kernel timing is enabled. Process-wide; not thread-safe against concurrent solves.
+ */
+void wd_set_graphs(int on);
 
 /* Bytes of device memory held by a handle (links and cached workspaces). */
 size_t wd_gauge_device_bytes(const wd_gauge* g);

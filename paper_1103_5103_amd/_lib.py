@@ -21,7 +21,7 @@ LIBPATH = os.path.join(_HERE, "libwdirac.so")
 
 WD_OK, WD_ERR_ARG, WD_ERR_HIP, WD_ERR_OOM, WD_ERR_NOCONV, WD_ERR_BREAKDOWN, WD_ERR_NAN, WD_ERR_UNSUPPORTED = range(8)
 WD_F64, WD_F32, WD_F16, WD_BF16 = range(4)
-WD_METHOD_SEQUENTIAL, WD_METHOD_MULTISHIFT = 0, 1
+WD_METHOD_SEQUENTIAL, WD_METHOD_MULTISHIFT, WD_METHOD_BATCHED = 0, 1, 2
 WD_GUESS_NONE, WD_GUESS_POLY = 0, 1
 PREC = {"f64": WD_F64, "f32": WD_F32, "f16": WD_F16, "bf16": WD_BF16}
 
@@ -67,6 +67,7 @@ EXPORTED = [
     "wd_params_default", "wd_gauge_create", "wd_gauge_destroy", "wd_apply", "wd_apply_dag", "bicgstab_solve",
     "bicgstab_m_solve", "wd_multimass_solve", "wd_batch_solve", "wd_gauge_grad", "wd_status_str",
     "wd_last_error", "wd_timing_enable", "wd_timing_reset", "wd_timing_get", "wd_gauge_device_bytes",
+    "wd_set_graphs",
 ]
 
 _lib = None
@@ -109,6 +110,8 @@ def load(path: str = LIBPATH):
     L.wd_timing_reset.argtypes = []
     L.wd_timing_reset.restype = None
     L.wd_timing_get.argtypes = [i, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_long), ctypes.POINTER(d)]
+    L.wd_set_graphs.argtypes = [i]
+    L.wd_set_graphs.restype = None
     L.wd_gauge_device_bytes.argtypes = [vp]
     L.wd_gauge_device_bytes.restype = ctypes.c_size_t
     for name in ("wd_gauge_create", "wd_gauge_destroy", "wd_apply", "wd_apply_dag", "bicgstab_solve",
@@ -295,6 +298,11 @@ def wd_gauge_grad(g: Gauge, x: torch.Tensor, lam: torch.Tensor, project: bool = 
     _check(load().wd_gauge_grad(g.handle, _ptr(x, "x", g.field_shape), _ptr(lam, "lam", g.field_shape),
                                 _ptr(out, "dU", g.link_shape), int(bool(project)), _stream()))
     return out
+
+
+def set_graphs(on: bool = True):
+    """Replay solver iteration chunks from captured HIP graphs, or launch eagerly (default)."""
+    load().wd_set_graphs(int(bool(on)))
 
 
 def timing_enable(on: bool = True):

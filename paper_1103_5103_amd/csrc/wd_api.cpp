@@ -16,6 +16,7 @@ wd_status solve_batch(int nsys, const wd_system* sys, const wd_solver_params& P,
                       hipStream_t st);
 wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* const* x, const double* b, int method,
                           int guess, const wd_solver_params& P, wd_solver_stats* stats, hipStream_t st);
+void set_graphs(bool on);
 } // namespace wd
 
 using namespace wd;
@@ -273,6 +274,8 @@ wd_status wd_gauge_grad(wd_gauge* g, const double* x, const double* lam, double*
         return WD_OK;
     });
 }
+
+void wd_set_graphs(int on) { set_graphs(on != 0); }
 
 void wd_timing_enable(int on)
 {

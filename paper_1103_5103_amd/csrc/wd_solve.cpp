@@ -28,6 +28,38 @@ static double now_s()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// ---------------------------------------------------------------- HIP graphs
+// A chunk of `poll` solver iterations is captured once per solve on a private stream and replayed
+// with hipGraphLaunch on the caller's stream. The captured kernels read only device-resident job
+// tables and scalars, so every replay continues from the current device state. Per-kernel timing
+// needs one event pair per launch, so graphs are not used while it is on.
+static bool g_graphs = false;
+
+struct ChunkGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    template <class F>
+    void capture(F&& body)
+    {
+        WD_CHECK_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        WD_CHECK_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        body(cap);
+        WD_CHECK_HIP(hipStreamEndCapture(cap, &graph));
+        WD_CHECK_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    void launch(hipStream_t st) { WD_CHECK_HIP(hipGraphLaunch(exec, st)); }
+    ~ChunkGraph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+void set_graphs(bool on) { g_graphs = on; }
+bool graphs_on() { return g_graphs && !timer().on; }
+
 static double spinor_site_bytes(int sf) { return sf == SF64 ? 192.0 : sf == SF32 ? 96.0 : 52.0; }
 static double link_site_bytes(int lf) { return 8.0 * link_chunks(lf) * link_chunk_bytes(lf); }
 
@@ -295,7 +327,9 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         const void* d0 = e.g->lk(L64_18, 0);
         const void* d1 = e.g->lk(L64_18, 1);
         const long lcs = e.g->lcs();
-        if (e.src.bb < 0) {
+        bool shared = false;  // another system of this solve already prepares the same source
+        for (int k = 0; k < i; k++) shared = shared || S[k].src.B64.base() == e.src.B64.base();
+        if (e.src.bb < 0 && !shared) {
             need_src.push_back(i);
             // h = 1/2 D_eo b_o ; |b|^2
             Hhb.host.push_back(hop_job(g, 0, i, e.src.B64.half(1), e.src.HB.all(), d0, lcs, 0.5));
@@ -395,6 +429,9 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         run_sweep(OP_NORM, SF64, Nb, sys.d(), 0, st, sweep_bytes(Nb, 192));
         sys.download(st);
         for (int i : need_src) S[i].src.bb = sys.h[i].red[2];
+        for (int i = 0; i < n; i++)
+            for (int k : need_src)
+                if (S[i].src.bb < 0 && S[i].src.B64.base() == S[k].src.B64.base()) S[i].src.bb = S[k].src.bb;
     }
     bool any_x0 = false;
     for (auto& e : S) {
@@ -436,15 +473,20 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     const double bH1 = hop_bytes(H1, SFL, LFL, 0), bH2 = hop_bytes(H2, SFL, LFL, 2), bH4 = hop_bytes(H4, SFL, LFL, 1);
     const double bSW = sweep_bytes(SW, 3 * bl), bSXR = sweep_bytes(SXR, 2 * bx + 5 * bl), bSS = sweep_bytes(SS, 4 * bl);
 
-    auto iterate = [&]() {
-        run_hop(SFL, LFL, false, RED_NONE, FIN_STORE, H1, sys.d(), 1, st, bH1);
-        run_hop(SFL, LFL, false, RED_ZDOT, FIN_BETA, H2, sys.d(), 1, st, bH2);
-        run_sweep(OP_W, SFL, SW, sys.d(), 1, st, bSW);
-        run_hop(SFL, LFL, false, RED_NONE, FIN_STORE, H3, sys.d(), 1, st, bH1);
-        run_hop(SFL, LFL, false, RED_OUTX, FIN_CHI, H4, sys.d(), 1, st, bH4);
-        run_sweep(OP_XR, SFL, SXR, sys.d(), 1, st, bSXR);
-        run_sweep(OP_S, SFL, SS, sys.d(), 1, st, bSS);
+    auto iterate = [&](hipStream_t q) {
+        run_hop(SFL, LFL, false, RED_NONE, FIN_STORE, H1, sys.d(), 1, q, bH1);
+        run_hop(SFL, LFL, false, RED_ZDOT, FIN_BETA, H2, sys.d(), 1, q, bH2);
+        run_sweep(OP_W, SFL, SW, sys.d(), 1, q, bSW);
+        run_hop(SFL, LFL, false, RED_NONE, FIN_STORE, H3, sys.d(), 1, q, bH1);
+        run_hop(SFL, LFL, false, RED_OUTX, FIN_CHI, H4, sys.d(), 1, q, bH4);
+        run_sweep(OP_XR, SFL, SXR, sys.d(), 1, q, bSXR);
+        run_sweep(OP_S, SFL, SS, sys.d(), 1, q, bSS);
     };
+    ChunkGraph graph;
+    if (graphs_on())
+        graph.capture([&](hipStream_t q) {
+            for (int k = 0; k < poll; k++) iterate(q);
+        });
     // tables restricted to a subset of the systems (the full tables when the subset is all)
     auto subset = [&](const auto& full, const std::vector<int>& ids) {
         std::remove_const_t<std::remove_reference_t<decltype(full)>> t;
@@ -475,7 +517,9 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     long host_iters = 0;
     const long host_cap = (long)P.max_iter + 16L * poll + 64;
     while (active > 0) {
-        for (int k = 0; k < poll; k++) iterate();
+        if (graph.exec) graph.launch(st);
+        else
+            for (int k = 0; k < poll; k++) iterate(st);
         host_iters += poll;
         sys.download(st);
         if (host_iters > host_cap) {
@@ -701,13 +745,18 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
 
     const int endop = ns > 0 ? OP_SHIFT : OP_S;
     const double bH = hop_bytes(HAs, SF64, L64_18, 2);
-    auto iterate = [&](int active_shifts) {
-        run_hop(SF64, L64_18, false, RED_ZDOT, FIN_BETA, HAs, sys.d(), 1, st, bH);
-        run_sweep(OP_W, SF64, SW, sys.d(), 1, st, sweep_bytes(SW, 3 * 192));
-        run_hop(SF64, L64_18, false, RED_OUTX, FIN_CHI, HAw, sys.d(), 1, st, bH - nsites * 192.0 / 2);
-        run_sweep(OP_XR, SF64, SXR, sys.d(), 1, st, sweep_bytes(SXR, 7 * 192));
-        run_sweep(endop, SF64, SEND, sys.d(), 1, st, sweep_bytes(SEND, (ns > 0 ? 6 : 4) * 192 + 4 * 192 * active_shifts));
+    auto iterate = [&](int active_shifts, hipStream_t q) {
+        run_hop(SF64, L64_18, false, RED_ZDOT, FIN_BETA, HAs, sys.d(), 1, q, bH);
+        run_sweep(OP_W, SF64, SW, sys.d(), 1, q, sweep_bytes(SW, 3 * 192));
+        run_hop(SF64, L64_18, false, RED_OUTX, FIN_CHI, HAw, sys.d(), 1, q, bH - nsites * 192.0 / 2);
+        run_sweep(OP_XR, SF64, SXR, sys.d(), 1, q, sweep_bytes(SXR, 7 * 192));
+        run_sweep(endop, SF64, SEND, sys.d(), 1, q, sweep_bytes(SEND, (ns > 0 ? 6 : 4) * 192 + 4 * 192 * active_shifts));
     };
+    ChunkGraph graph;
+    if (graphs_on())
+        graph.capture([&](hipStream_t q) {
+            for (int k = 0; k < poll; k++) iterate(ns, q);
+        });
     int status = WD_OK;
     int active_shifts = ns;
     long host_iters = 0;
@@ -715,7 +764,9 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
     while (true) {
         if (sys.h[0].status != ST_RUNNING) break;
         if (host_iters > host_cap) break;  // no exit state reported by the device
-        for (int k = 0; k < poll; k++) iterate(active_shifts);
+        if (graph.exec) graph.launch(st);
+        else
+            for (int k = 0; k < poll; k++) iterate(active_shifts, st);
         host_iters += poll;
         sys.download(st);
         if (ns > 0) {
@@ -848,6 +899,38 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
     WD_REQUIRE(n >= 1 && n <= 32, "number of masses must be in 1..32");
     for (int i = 0; i < n; i++) WD_REQUIRE(kappas[i] > 0, "kappa must be positive");
     if (method == WD_METHOD_MULTISHIFT) return solve_multishift(g, n, kappas, x, b, P, stats, st);
+    if (method == WD_METHOD_BATCHED) {
+        // every mass is its own single-mass system; all iterate together, one launch per solver
+        // step, sharing one packed source (no start guesses: the masses are solved simultaneously)
+        WD_REQUIRE(P.eo, "batched solves use even-odd preconditioning");
+        WD_REQUIRE(guess == WD_GUESS_NONE || guess == WD_GUESS_POLY, "unknown guess");
+        EoSource src;
+        prepare_source(g, "mm.", b, P.dagger, src, st);
+        std::vector<EoSys> S(n);
+        for (int i = 0; i < n; i++) {
+            S[i].g = g;
+            S[i].kappa = kappas[i];
+            S[i].b = b;
+            S[i].x = x[i];
+            S[i].slot = i;
+            S[i].src = src;
+        }
+        wd_solver_params Q = P;
+        Q.use_x0 = 0;
+        eo_solve(S, Q, st, 4);
+        wd_status worst = WD_OK;
+        for (int i = 0; i < n; i++) {
+            if (stats) {
+                stats[i].iters = S[i].iters;
+                stats[i].reliable_updates = S[i].reliable;
+                stats[i].status = S[i].final_status;
+                stats[i].true_rel_res = S[i].true_rel;
+                stats[i].seconds = S[i].t1 - S[i].t0;
+            }
+            if (S[i].final_status != WD_OK && worst == WD_OK) worst = (wd_status)S[i].final_status;
+        }
+        return worst;
+    }
     WD_REQUIRE(method == WD_METHOD_SEQUENTIAL, "unknown method");
     WD_REQUIRE(guess == WD_GUESS_NONE || guess == WD_GUESS_POLY, "unknown guess");
     std::vector<int> order(n);

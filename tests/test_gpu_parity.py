@@ -199,6 +199,11 @@ def test_multimass_sequential_poly_guess():
                                     p=wd.params(tol=1e-8, mixed=False, eo=False))
     for k, x in zip(kappas, xm):
         assert oracle.true_residual(U, k, _n(x), b) < 1.5e-8
+    xb, stb = wd.wd_multimass_solve(g, kappas, bd, method=wd.WD_METHOD_BATCHED)
+    for k, x, s in zip(kappas, xb, stb):
+        assert s["status"] == 0 and oracle.true_residual(U, k, _n(x), b) < 1e-8
+    # heavier masses converge in fewer iterations and drop out of the batch first
+    assert stb[0]["iters"] <= stb[-1]["iters"]
     g.close()
 
 
@@ -287,3 +292,31 @@ def test_odd_extent_rejected():
     with pytest.raises(wd.WdError) as e:
         wd.wd_gauge_create(U)
     assert e.value.code == 1
+
+
+# ------------------------------------------------------------------ graph replays
+
+def test_graph_replays_match_eager_launches():
+    """Each solve replays its captured iteration chunk many times, with eager reliable updates and
+    host synchronisations in between; with deterministic reductions the result must be bitwise
+    equal to launching every kernel eagerly."""
+    dims = (8, 8, 8, 16)
+    U = li.random_links(dims, 1.0, 1070)
+    b = li.gaussian_field(dims, 2070)
+    g = wd.wd_gauge_create(_t(U))
+    bd = _t(b)
+    kappas = [0.124, 0.128, 0.132]
+    out = {}
+    try:
+        for mode in (True, False):
+            wd.set_graphs(mode)
+            x1, s1 = wd.bicgstab_solve(g, 0.13, bd, p=wd.params(tol=1e-9, spinor="f16", links="bf16", delta=0.1))
+            xm, sm = wd.bicgstab_m_solve(g, kappas, bd, p=wd.params(tol=1e-10, mixed=False, eo=False))
+            xs, ss = wd.wd_multimass_solve(g, kappas, bd)
+            out[mode] = [x1] + xm + xs
+            assert s1["reliable_updates"] >= 2
+    finally:
+        wd.set_graphs(False)
+    for a, c in zip(out[True], out[False]):
+        assert torch.equal(a, c)
+    g.close()
