@@ -8,8 +8,9 @@ solve of the same 8 masses on the full lattice, all to relative residual 1e-8. I
 seeded; they stand in for the paper's quenched ensemble, which is not available.
 
 The reported value is the low-precision dslash (even-odd hop) throughput: algorithmic bytes of
-every hop launch in the timed steps divided by their durations, measured with HIP events on the
-launch stream. Per output site a hop moves the input spinor, the output spinor and 8 links
+every hop launch divided by their durations, measured with HIP events on the launch stream during
+a second pass over the same steps (per-kernel events slow small solves, so the solve wall times and
+ms_per_step come from the first, uninstrumented pass). Per output site a hop moves the input spinor, the output spinor and 8 links
 (96 + 96 + 8 x 24 = 384 B with FP32 spinors and FP16 12-real links) plus the epilogue fields it
 reads. The CPU baseline is the plain FP64 oracle on the host cores.
 
@@ -35,7 +36,7 @@ WORKLOADS = {
                   name="32^3x64 even-odd Wilson, 8 masses kappa 0.120..0.134, near-Haar SU(3) links, FP16 12-real "
                        "links, FP32 spinors, FP64 reliable updates, 1 Gaussian source"),
     "16x32": dict(dims=(16, 16, 16, 32), kappas=[0.120, 0.122, 0.124, 0.126, 0.128, 0.130], eps=1.0,
-                  link_seed=1001, src_seed=2001, links="f16", spinor="f16", delta=0.1,
+                  link_seed=1001, src_seed=2001, links="f16", spinor="f16", delta=0.03,
                   name="16^3x32 even-odd Wilson, 6 masses kappa 0.120..0.130, near-Haar SU(3) links, FP16 12-real "
                        "links, FP16 spinors, FP64 reliable updates, 1 Gaussian source"),
 }
@@ -174,8 +175,7 @@ def main():
         r = step()
         log(f"warmup {i}: mixed sequential {r[0]:.4f}s, mixed batched {r[4]:.4f}s, FP64 BiCGstab-M {r[1]:.4f}s")
     peak_va = practical_peak(torch, dev)
-    wd.timing_reset()
-    wd.timing_enable(True)
+    # timed region 1: the steps as a user runs them (no per-kernel instrumentation)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     results = []
@@ -185,6 +185,12 @@ def main():
         log(f"step {i}: mixed sequential {r[0]:.4f}s, mixed batched {r[4]:.4f}s, FP64 BiCGstab-M {r[1]:.4f}s")
     torch.cuda.synchronize()
     t_end = time.perf_counter()
+    # timed region 2: the same steps with every kernel bracketed by HIP events on its stream
+    wd.timing_reset()
+    wd.timing_enable(True)
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
     hop_ms, hop_n, hop_bytes = wd.timing_get(0)
     f64_ms, f64_n, f64_bytes = wd.timing_get(1)
     sw_ms, sw_n, sw_bytes = wd.timing_get(2)

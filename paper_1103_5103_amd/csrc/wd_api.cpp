@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <vector>
 
 #include "wd_host.hpp"
 
@@ -128,6 +129,21 @@ wd_status wd_gauge_create(wd_gauge** out, const wd_geom* geom, const double* U, 
         g->links[L64_18] = std::make_unique<DevMem>(lb);
         WD_CHECK_HIP(hipMemsetAsync(g->links[L64_18]->p, 0, lb, s));
         WD_CHECK_HIP(launch_pack_links(U, G, g->links[L64_18]->p, (char*)g->links[L64_18]->p + lb / 2, G.stride, s));
+        {
+            // decide whether the 12-real FP64 format is exact for these links
+            const int nb = (G.Vh + BLOCK - 1) / BLOCK;
+            DevMem bm(sizeof(double) * nb);
+            double e = 0.0;
+            std::vector<double> h(nb);
+            for (int p = 0; p < 2; p++) {
+                WD_CHECK_HIP(launch_recon_check(g->lk(L64_18, p), G.Vh, G.stride, (double*)bm.p, s));
+                WD_CHECK_HIP(hipMemcpyAsync(h.data(), bm.p, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+                WD_CHECK_HIP(hipStreamSynchronize(s));
+                for (double v : h) e = std::max(e, std::isfinite(v) ? v : 1.0);
+            }
+            g->recon_err = e;
+            if (e < 1e-12) g->ensure_links(L64_12, s);
+        }
         if (hint && hint->mixed) g->ensure_links(link_fmt_of(hint->link_store, hint->recon), s);
         WD_CHECK_HIP(hipStreamSynchronize(s));
         *out = g.release();

@@ -69,7 +69,7 @@ size_t field_bytes(int sf, int halves, long stride);
 enum { TK_HOP_LO = 0, TK_HOP_F64 = 1, TK_SWEEP = 2, TK_FINISH = 3, NTK = 4 };
 struct Timer {
     bool on = false;
-    struct Rec { int cls; hipEvent_t a, b; double bytes; int slot; };
+    struct Rec { int cls; hipEvent_t a, b; double bytes; int slot; int njobs; };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
     int* dflags = nullptr;  // per pending launch: set by the kernel when it did work
@@ -108,6 +108,9 @@ struct wd_gauge {
     std::map<std::string, std::shared_ptr<wd::DevMem>> raw;
     std::map<std::string, wd::JobTable<wd::HopJob>> hop_tables;
     hipStream_t stream = nullptr;
+    double recon_err = 1.0;  // max |row2 - conj(row0 x row1)| over the links
+    // FP64 operator format: 12-real when the links are SU(3) to rounding, else 18-real
+    int f64_links() const { return recon_err < 1e-12 ? wd::L64_12 : wd::L64_18; }
     const void* lk(int lf, int parity) const;
     long lcs() const { return geo.stride; }
     wd::Field& field(const std::string& key, int sf, int halves);

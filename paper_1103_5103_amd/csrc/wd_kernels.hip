@@ -328,7 +328,7 @@ __global__ __launch_bounds__(BLOCK, HopWaves<SF>::W > 0 ? HopWaves<SF>::W : 1) v
     SysState* S = sys + J.sys;
     if (gated && S->status != ST_RUNNING) return;
     const int lb = b - J.blk0;
-    if (exec && lb == 0 && threadIdx.x == 0) atomicOr(exec, 1);  // timing: this launch did work
+    if (exec && lb == 0 && threadIdx.x == 0) atomicAdd(exec, 1);  // timing: jobs that did work
     const int cb = tiled_block(J, lb) * BLOCK + threadIdx.x;
     double v[NRED] = {0.0, 0.0, 0.0, 0.0};
     if (cb < J.g.Vh) {
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
     SysState* S = sys + J.sys;
     if (gated && S->status != ST_RUNNING) return;
     const int lb = b - J.blk0;
-    if (exec && lb == 0 && threadIdx.x == 0) atomicOr(exec, 1);
+    if (exec && lb == 0 && threadIdx.x == 0) atomicAdd(exec, 1);
     const long i = (long)lb * BLOCK + threadIdx.x;
     const bool ok = i < J.n;
     double v[NRED] = {0.0, 0.0, 0.0, 0.0};
@@ -688,6 +688,40 @@ __global__ __launch_bounds__(BLOCK) void k_convert_links(const void* __restrict_
     cx<double> W[9];
     load_link<L64_18, double>(src, lcs, k, cb, W);
     store_link<LF>(dst, lcs, k, cb, W);
+}
+
+// Largest deviation of row 2 from conj(row0 x row1) over all stored links (per block), which
+// decides whether the 12-real FP64 format reproduces the operator exactly.
+__global__ __launch_bounds__(BLOCK) void k_recon_check(const void* __restrict__ lk, int Vh, long lcs,
+                                                       double* __restrict__ blockmax)
+{
+    __shared__ double lds[BLOCK / 64];
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    double m = 0.0;
+    if (cb < Vh) {
+        for (int k = 0; k < 8; k++) {
+            cx<double> W[9];
+            load_link<L64_18, double>(lk, lcs, k, cb, W);
+            cx<double> R[9];
+            for (int j = 0; j < 6; j++) R[j] = W[j];
+            recon_row2(R);
+            for (int j = 6; j < 9; j++) m = fmax(m, fmax(fabs(R[j].re - W[j].re), fabs(R[j].im - W[j].im)));
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < BLOCK / 64; w++) m = fmax(m, lds[w]);
+        blockmax[blockIdx.x] = m;
+    }
+}
+
+hipError_t launch_recon_check(const void* lk, int Vh, long lcs, double* blockmax, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_recon_check, dim3((unsigned)((Vh + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, lk, Vh, lcs,
+                       blockmax);
+    return hipGetLastError();
 }
 
 // out = sum_j c_j in_j over n complex numbers (FP64, any layout)

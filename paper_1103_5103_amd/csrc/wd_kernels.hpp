@@ -8,7 +8,7 @@ enum HopRed { RED_NONE = 0, RED_ZDOT = 1, RED_OUTX = 2, RED_NORM = 3 };
 enum SweepOp { OP_W = 0, OP_XR = 1, OP_S = 2, OP_SHIFT = 3, OP_INIT = 4, OP_ACC = 5, OP_NORM = 6, OP_MSINIT = 7, OP_AXPY = 8,
                OP_LINCOMB = 9 };
 
-// exec (may be NULL): set to 1 by the launch if any system in it was not gated off
+// exec (may be NULL): incremented once per job that was not gated off
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
                       SysState* sys, int gated, hipStream_t s, int* exec = nullptr);
 hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState* sys, int gated, hipStream_t s);
@@ -20,6 +20,7 @@ hipError_t launch_unpack_spinor(int sf, double* dst, const Geo& g, SpinorRef eve
                                 double scale, hipStream_t s);
 hipError_t launch_pack_links(const double* U, const Geo& g, void* even, void* odd, long lcs, hipStream_t s);
 hipError_t launch_convert_links(int lf, const void* src, void* dst, int Vh, long lcs, hipStream_t s);
+hipError_t launch_recon_check(const void* lk, int Vh, long lcs, double* blockmax, hipStream_t s);
 hipError_t launch_lincomb(double* out, const double* const* ins, const double* c, int k, long ncomplex, hipStream_t s);
 hipError_t launch_grad(const double* x, const double* lam, const Geo& g, const void* lk_even, const void* lk_odd,
                        long lcs, double* out, int project, hipStream_t s);

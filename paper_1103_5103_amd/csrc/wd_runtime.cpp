@@ -1,5 +1,6 @@
 // Runtime pieces of libwdirac: device memory, workspace fields, link preparation, job-table
 // upload, launch helpers with optional HIP-event timing, and the thread-local error message.
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 
@@ -101,7 +102,8 @@ int* Timer::slot()
 }
 
 // Launches that every system skipped (gated iterations after convergence) are not counted:
-// their kernels ran for a few microseconds and moved no data.
+// their kernels ran for a few microseconds and moved no data. A launch in which only some jobs
+// ran is credited that fraction of its bytes (exact when the jobs have equal sizes).
 void Timer::flush()
 {
     if (pending.empty()) return;
@@ -117,7 +119,8 @@ void Timer::flush()
             float t = 0;
             WD_CHECK_HIP(hipEventElapsedTime(&t, r.a, r.b));
             ms[r.cls] += t;
-            bytes[r.cls] += r.bytes;
+            const double frac = (r.slot < 0 || r.njobs <= 0) ? 1.0 : std::min(1.0, (double)done[k] / r.njobs);
+            bytes[r.cls] += r.bytes * frac;
             launches[r.cls] += 1;
         }
         pool.push_back(r.a);
@@ -186,7 +189,7 @@ static void run_finish(int nr, int fin, const JobTable<J>& t, SysState* sys, int
     WD_CHECK_HIP(launch_finish(nr, fin, t.fin_d(), (int)t.fin.size(), sys, gated, s));
     if (T.on) {
         WD_CHECK_HIP(hipEventRecord(b, s));
-        T.pending.push_back({TK_FINISH, a, b, 0.0, -1});
+        T.pending.push_back({TK_FINISH, a, b, 0.0, -1, 0});
     }
 }
 
@@ -206,7 +209,7 @@ void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>&
     WD_CHECK_HIP(launch_hop(sf, lf, dag, red, fin, t.d(), t.n(), t.nblocks, sys, gated, s, flag));
     if (T.on) {
         WD_CHECK_HIP(hipEventRecord(b, s));
-        T.pending.push_back({cls, a, b, bytes, (int)(flag - T.dflags)});
+        T.pending.push_back({cls, a, b, bytes, (int)(flag - T.dflags), t.n()});
     }
     if (red != RED_NONE) run_finish(3, fin, t, sys, gated, s);
 }
@@ -225,7 +228,7 @@ void run_sweep(int op, int sfl, const JobTable<SweepJob>& t, SysState* sys, int 
     WD_CHECK_HIP(launch_sweep(op, sfl, t.d(), t.n(), t.nblocks, sys, gated, s, flag));
     if (T.on) {
         WD_CHECK_HIP(hipEventRecord(b, s));
-        T.pending.push_back({TK_SWEEP, a, b, bytes, (int)(flag - T.dflags)});
+        T.pending.push_back({TK_SWEEP, a, b, bytes, (int)(flag - T.dflags), t.n()});
     }
     switch (op) {
     case OP_XR: run_finish(3, FIN_ALPHA, t, sys, gated, s); break;

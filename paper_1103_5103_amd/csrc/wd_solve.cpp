@@ -272,13 +272,23 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     const int n = (int)S.size();
     const int SFL = P.mixed ? spinor_fmt_of(P.spinor_store) : SF64;
     const int SFX = SFL == SF64 ? SF64 : SF32;
-    const int LFL = P.mixed ? link_fmt_of(P.link_store, P.recon) : L64_18;
+    // the FP64 operator (b_prec, reliable updates, eq. eo3) uses 12-real links when every handle's
+    // links are SU(3) to rounding; the iteration uses the low-precision format
+    int L64 = L64_12;
+    for (auto& e : S)
+        if (e.g->f64_links() != L64_12) L64 = L64_18;
+    const int LFL = P.mixed ? link_fmt_of(P.link_store, P.recon) : L64;
+    if (P.mixed && link_recon12(LFL))
+        for (auto& e : S)
+            if (e.g->recon_err > 1e-6)
+                throw Error{WD_ERR_UNSUPPORTED, "links are not SU(3): the 12-real low-precision formats would change "
+                                                "the operator; solve with mixed = 0"};
     const double t_start = now_s();
 
     std::vector<int> tile_lo(n), tile_64(n);
     for (int i = 0; i < n; i++) {
         tile_lo[i] = tune_tile(S[i].g, SFL, LFL, st);
-        tile_64[i] = tune_tile(S[i].g, SF64, L64_18, st);
+        tile_64[i] = tune_tile(S[i].g, SF64, L64, st);
     }
     for (auto& e : S) {
         e.g->ensure_links(LFL, st);
@@ -324,8 +334,8 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     for (int i = 0; i < n; i++) {
         EoSys& e = S[i];
         const Geo& g = e.g->geo;
-        const void* d0 = e.g->lk(L64_18, 0);
-        const void* d1 = e.g->lk(L64_18, 1);
+        const void* d0 = e.g->lk(L64, 0);
+        const void* d1 = e.g->lk(L64, 1);
         const long lcs = e.g->lcs();
         bool shared = false;  // another system of this solve already prepares the same source
         for (int k = 0; k < i; k++) shared = shared || S[k].src.B64.base() == e.src.B64.base();
@@ -425,7 +435,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
 
     // ---- setup
     if (!need_src.empty()) {
-        run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, Hhb, sys.d(), 0, st, hop_bytes(Hhb, SF64, L64_18, 0));
+        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hhb, sys.d(), 0, st, hop_bytes(Hhb, SF64, L64, 0));
         run_sweep(OP_NORM, SF64, Nb, sys.d(), 0, st, sweep_bytes(Nb, 192));
         sys.download(st);
         for (int i : need_src) S[i].src.bb = sys.h[i].red[2];
@@ -445,8 +455,8 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     run_sweep(OP_AXPY, SF64, Bp, sys.d(), 0, st, sweep_bytes(Bp, 3 * 192));
     if (any_x0) {
         // start vector: r_hi = b_prec - M_prec x0 (systems without one have x0 = 0 and get b_prec)
-        run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, Hx1, sys.d(), 0, st, hop_bytes(Hx1, SF64, L64_18, 0));
-        run_hop(SF64, L64_18, false, RED_NORM, FIN_STORE, Hx2, sys.d(), 0, st, hop_bytes(Hx2, SF64, L64_18, 2));
+        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hx1, sys.d(), 0, st, hop_bytes(Hx1, SF64, L64, 0));
+        run_hop(SF64, L64, false, RED_NORM, FIN_STORE, Hx2, sys.d(), 0, st, hop_bytes(Hx2, SF64, L64, 2));
     }
     sys.download(st);
     for (int i = 0; i < n; i++) {
@@ -499,16 +509,16 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     auto reliable_update = [&](const std::vector<int>& ids) {
         if ((int)ids.size() == n) {
             run_sweep(OP_ACC, SFL, Acc, sys.d(), 0, st, sweep_bytes(Acc, 2 * 192 + 2 * bx));
-            run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, Hx1, sys.d(), 0, st, hop_bytes(Hx1, SF64, L64_18, 0));
-            run_hop(SF64, L64_18, false, RED_NORM, FIN_STORE, Hx2, sys.d(), 0, st, hop_bytes(Hx2, SF64, L64_18, 2));
+            run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hx1, sys.d(), 0, st, hop_bytes(Hx1, SF64, L64, 0));
+            run_hop(SF64, L64, false, RED_NORM, FIN_STORE, Hx2, sys.d(), 0, st, hop_bytes(Hx2, SF64, L64, 2));
             return;
         }
         auto A = subset(Acc, ids);
         auto X1 = subset(Hx1, ids);
         auto X2 = subset(Hx2, ids);
         run_sweep(OP_ACC, SFL, A, sys.d(), 0, st, sweep_bytes(A, 2 * 192 + 2 * bx));
-        run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, X1, sys.d(), 0, st, hop_bytes(X1, SF64, L64_18, 0));
-        run_hop(SF64, L64_18, false, RED_NORM, FIN_STORE, X2, sys.d(), 0, st, hop_bytes(X2, SF64, L64_18, 2));
+        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, X1, sys.d(), 0, st, hop_bytes(X1, SF64, L64, 0));
+        run_hop(SF64, L64, false, RED_NORM, FIN_STORE, X2, sys.d(), 0, st, hop_bytes(X2, SF64, L64, 2));
         WD_CHECK_HIP(hipStreamSynchronize(st));  // the subset tables are released on return
     };
 
@@ -600,7 +610,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     // ---- finish: odd half from eq. eo3, unpack. With x_o from eq. eo3 the full residual is
     // b - M x = (b_prec - M_prec x_e) / a on the even sites and exactly zero on the odd ones, so
     // the last FP64 residual gives the true relative residual without another operator pass.
-    run_hop(SF64, L64_18, false, RED_NONE, FIN_STORE, Hrec, sys.d(), 0, st, hop_bytes(Hrec, SF64, L64_18, 1));
+    run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hrec, sys.d(), 0, st, hop_bytes(Hrec, SF64, L64, 1));
     for (auto& e : S)
         WD_CHECK_HIP(launch_unpack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st));
     sys.download(st);
@@ -641,6 +651,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
         SS[k] = g->field("ms.SS" + std::to_string(k), SF64, 2);
     }
     const Geo& geo = g->geo;
+    const int L64 = g->f64_links();
 
     SysArray sys;
     sys.alloc(1);
@@ -713,12 +724,12 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
     SEND.host.push_back(j);
     JobTable<HopJob> HAs, HAw;
     for (int p = 0; p < 2; p++) {
-        HopJob h = hop_job(geo, p, 0, Sv.half(1 - p), AS.half(p), g->lk(L64_18, p), g->lcs(), -0.5);
+        HopJob h = hop_job(geo, p, 0, Sv.half(1 - p), AS.half(p), g->lk(L64, p), g->lcs(), -0.5);
         h.x0 = Sv.half(p);
         h.c0 = a;
         h.z = B.half(p);
         HAs.host.push_back(h);
-        h = hop_job(geo, p, 0, W.half(1 - p), AW.half(p), g->lk(L64_18, p), g->lcs(), -0.5);
+        h = hop_job(geo, p, 0, W.half(1 - p), AW.half(p), g->lk(L64, p), g->lcs(), -0.5);
         h.x0 = W.half(p);
         h.c0 = a;
         HAw.host.push_back(h);
@@ -727,7 +738,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
         layout(*t);
         t->upload(st);
     }
-    const int tz64 = tune_tile(g, SF64, L64_18, st);
+    const int tz64 = tune_tile(g, SF64, L64, st);
     for (auto* t : {&HAs, &HAw}) {
         for (auto& h : t->host) set_tile(h, tz64);
         layout(*t);
@@ -744,11 +755,11 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
     sys.upload(st);
 
     const int endop = ns > 0 ? OP_SHIFT : OP_S;
-    const double bH = hop_bytes(HAs, SF64, L64_18, 2);
+    const double bH = hop_bytes(HAs, SF64, L64, 2);
     auto iterate = [&](int active_shifts, hipStream_t q) {
-        run_hop(SF64, L64_18, false, RED_ZDOT, FIN_BETA, HAs, sys.d(), 1, q, bH);
+        run_hop(SF64, L64, false, RED_ZDOT, FIN_BETA, HAs, sys.d(), 1, q, bH);
         run_sweep(OP_W, SF64, SW, sys.d(), 1, q, sweep_bytes(SW, 3 * 192));
-        run_hop(SF64, L64_18, false, RED_OUTX, FIN_CHI, HAw, sys.d(), 1, q, bH - nsites * 192.0 / 2);
+        run_hop(SF64, L64, false, RED_OUTX, FIN_CHI, HAw, sys.d(), 1, q, bH - nsites * 192.0 / 2);
         run_sweep(OP_XR, SF64, SXR, sys.d(), 1, q, sweep_bytes(SXR, 7 * 192));
         run_sweep(endop, SF64, SEND, sys.d(), 1, q, sweep_bytes(SEND, (ns > 0 ? 6 : 4) * 192 + 4 * 192 * active_shifts));
     };
@@ -802,7 +813,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
         const double ai = 1.0 / (2.0 * kappas[i]);
         JobTable<HopJob> R;
         for (int p = 0; p < 2; p++) {
-            HopJob h = hop_job(geo, p, 0, Xi.half(1 - p), RES.half(p), g->lk(L64_18, p), g->lcs(), 0.5);
+            HopJob h = hop_job(geo, p, 0, Xi.half(1 - p), RES.half(p), g->lk(L64, p), g->lcs(), 0.5);
             h.x0 = B.half(p);
             h.c0 = 1.0;
             h.x1 = Xi.half(p);
@@ -812,7 +823,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
         }
         layout(R);
         R.upload(st);
-        run_hop(SF64, L64_18, false, RED_NORM, FIN_STORE, R, sys.d(), 0, st, 0);
+        run_hop(SF64, L64, false, RED_NORM, FIN_STORE, R, sys.d(), 0, st, 0);
         WD_CHECK_HIP(launch_unpack_spinor(SF64, x[i], geo, Xi.half(0), Xi.half(1), P.dagger, 1.0, st));
         sys.download(st);
         if (stats) {

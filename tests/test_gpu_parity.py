@@ -287,6 +287,23 @@ def test_error_codes():
     g.close()
 
 
+def test_non_su3_links_use_the_exact_fp64_operator():
+    """Links that are not SU(3) cannot be rebuilt from two rows: the FP64 solve must then use all 18
+    reals (parity with the oracle on the same non-unitary field), and mixed precision with 12-real
+    links is refused."""
+    dims = (4, 4, 4, 8)
+    U = li.random_links(dims, 1.0, 1080) * 1.05
+    b = li.gaussian_field(dims, 2080)
+    g = wd.wd_gauge_create(_t(U))
+    for eo in (True, False):
+        x, st = wd.bicgstab_solve(g, 0.12, _t(b), p=wd.params(tol=1e-10, mixed=False, eo=eo))
+        assert oracle.true_residual(U, 0.12, _n(x), b) < 1e-10
+    with pytest.raises(wd.WdError) as e:
+        wd.bicgstab_solve(g, 0.12, _t(b))
+    assert e.value.code == 7
+    g.close()
+
+
 def test_odd_extent_rejected():
     U = torch.zeros((4, 4, 4, 4, 3, 3, 3), dtype=torch.complex128, device=DEV)
     with pytest.raises(wd.WdError) as e:
