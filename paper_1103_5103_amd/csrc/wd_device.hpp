@@ -116,6 +116,25 @@ __host__ __device__ __forceinline__ long chunk_at(int nchunks, long cs, long i, 
     else return j * cs + i;
 }
 
+// ---------------------------------------------------------------- global-memory accessors
+// Device pointers reach the kernels through job tables in memory, so the compiler cannot tell
+// they are global and would emit flat loads; these casts make every field and link access a
+// global load or store.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <class V>
+__device__ __forceinline__ V gld(const void* base, long idx)
+{
+    typedef __attribute__((address_space(1))) const V GV;
+    return *((GV*)base + idx);
+}
+template <class V>
+__device__ __forceinline__ void gst(void* base, long idx, V v)
+{
+    typedef __attribute__((address_space(1))) V GV;
+    *((GV*)base + idx) = v;
+}
+
 // ---------------------------------------------------------------- field views
 struct SpinorRef {
     void* p;     // chunk 0 of site 0 of this view
@@ -130,26 +149,23 @@ template <int SF, class T>
 __device__ __forceinline__ void load_spinor(const SpinorRef& r, long i, cx<T> v[12])
 {
     if constexpr (SF == SF64) {
-        const double2* p = (const double2*)r.p;
 #pragma unroll
         for (int j = 0; j < 12; j++) {
-            double2 q = p[chunk_at(12, r.cs, i, j)];
-            v[j] = mk<T>((T)q.x, (T)q.y);
+            d2v q = gld<d2v>(r.p, chunk_at(12, r.cs, i, j));
+            v[j] = mk<T>((T)q[0], (T)q[1]);
         }
     } else if constexpr (SF == SF32) {
-        const float4* p = (const float4*)r.p;
 #pragma unroll
         for (int j = 0; j < 6; j++) {
-            float4 q = p[chunk_at(6, r.cs, i, j)];
-            v[2 * j] = mk<T>((T)q.x, (T)q.y);
-            v[2 * j + 1] = mk<T>((T)q.z, (T)q.w);
+            f4v q = gld<f4v>(r.p, chunk_at(6, r.cs, i, j));
+            v[2 * j] = mk<T>((T)q[0], (T)q[1]);
+            v[2 * j + 1] = mk<T>((T)q[2], (T)q[3]);
         }
     } else {
-        const h8* p = (const h8*)r.p;
-        const float n = r.nrm[i];
+        const float n = gld<float>(r.nrm, i);
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            h8 q = p[chunk_at(3, r.cs, i, j)];
+            h8 q = gld<h8>(r.p, chunk_at(3, r.cs, i, j));
 #pragma unroll
             for (int k = 0; k < 4; k++) v[4 * j + k] = mk<T>((T)((float)q[2 * k] * n), (T)((float)q[2 * k + 1] * n));
         }
@@ -160,22 +176,19 @@ template <int SF, class T>
 __device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const cx<T> v[12])
 {
     if constexpr (SF == SF64) {
-        double2* p = (double2*)r.p;
 #pragma unroll
-        for (int j = 0; j < 12; j++) p[chunk_at(12, r.cs, i, j)] = make_double2((double)v[j].re, (double)v[j].im);
+        for (int j = 0; j < 12; j++) gst<d2v>(r.p, chunk_at(12, r.cs, i, j), d2v{(double)v[j].re, (double)v[j].im});
     } else if constexpr (SF == SF32) {
-        float4* p = (float4*)r.p;
 #pragma unroll
         for (int j = 0; j < 6; j++)
-            p[chunk_at(6, r.cs, i, j)] = make_float4((float)v[2 * j].re, (float)v[2 * j].im, (float)v[2 * j + 1].re,
-                                          (float)v[2 * j + 1].im);
+            gst<f4v>(r.p, chunk_at(6, r.cs, i, j),
+                     f4v{(float)v[2 * j].re, (float)v[2 * j].im, (float)v[2 * j + 1].re, (float)v[2 * j + 1].im});
     } else {
-        h8* p = (h8*)r.p;
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf((float)v[k].re), fabsf((float)v[k].im)));
         const float inv = m > 0.f ? 1.0f / m : 0.f;
-        r.nrm[i] = m;
+        gst<float>(r.nrm, i, m);
 #pragma unroll
         for (int j = 0; j < 3; j++) {
             h8 q;
@@ -184,7 +197,7 @@ __device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const c
                 q[2 * k] = (_Float16)((float)v[4 * j + k].re * inv);
                 q[2 * k + 1] = (_Float16)((float)v[4 * j + k].im * inv);
             }
-            p[chunk_at(3, r.cs, i, j)] = q;
+            gst<h8>(r.p, chunk_at(3, r.cs, i, j), q);
         }
     }
 }
@@ -198,11 +211,10 @@ __device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const c
 template <class V>
 __device__ __forceinline__ V ld_stream(const V* p)
 {
-    if constexpr (WD_NT_LINKS) return __builtin_nontemporal_load(p);
-    else return *p;
+    typedef __attribute__((address_space(1))) const V GV;
+    if constexpr (WD_NT_LINKS) return __builtin_nontemporal_load((GV*)p);
+    else return *(GV*)p;
 }
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef double d2v __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------- links
 __device__ __forceinline__ float bf16_to_f32(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
