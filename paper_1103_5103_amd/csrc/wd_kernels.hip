@@ -550,13 +550,13 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
         }
         write_partials<3>(v, S, J.rblk0 + lb);
     } else if constexpr (OP == OP_AXPY) {
-        // f0 = c0 f1 + f2 (FP64)
+        // f0 = c0 f1 + c1 f2 (FP64)
         if (ok) {
             cx<double> a[12], bq[12];
             load_spinor<SF64, double>(J.f[R_F1], i, a);
             load_spinor<SF64, double>(J.f[R_F2], i, bq);
 #pragma unroll
-            for (int k = 0; k < 12; k++) a[k] = J.c[0] * a[k] + bq[k];
+            for (int k = 0; k < 12; k++) a[k] = J.c[0] * a[k] + J.c[1] * bq[k];
             store_spinor<SF64, double>(J.f[R_F0], i, a);
         }
     } else if constexpr (OP == OP_LINCOMB) {

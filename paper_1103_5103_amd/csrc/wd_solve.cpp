@@ -327,7 +327,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
 
     // ---- static job tables
     JobTable<HopJob> Hhb, Hx1, Hx2, Hrec;
-    JobTable<SweepJob> Nb, Bp, InitFirst, InitRel, InitRestart, Acc;
+    JobTable<SweepJob> Nb, Bp, InitFirst, InitRel, InitRestart, Acc, Odd;
     JobTable<HopJob> H1, H2, H3, H4;
     JobTable<SweepJob> SW, SXR, SS;
     std::vector<int> need_src;
@@ -353,7 +353,17 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         bj.f[R_F1] = e.src.B64.half(0);
         bj.f[R_F2] = e.src.HB.all();
         bj.c[0] = e.a;
+        bj.c[1] = 1.0;
         Bp.host.push_back(bj);
+        // odd half from the last FP64 residual update, which left T64 = D_oe x_e:
+        // x_o = (b_o + 1/2 D_oe x_e) / a  (eq. eo3)
+        bj = sweep_job(i, e.T64.nsites());
+        bj.f[R_F0] = e.X64.half(1);
+        bj.f[R_F1] = e.src.B64.half(1);
+        bj.f[R_F2] = e.T64.all();
+        bj.c[0] = 1.0 / e.a;
+        bj.c[1] = 0.5 / e.a;
+        Odd.host.push_back(bj);
         // FP64 residual r_hi = b_prec - M_prec x_e: T64 = D_oe x_e ; RH = b_prec - a^2 x_e + 1/4 D_eo T64
         Hx1.host.push_back(hop_job(g, 1, i, e.X64.half(0), e.T64.all(), d1, lcs, 1.0));
         HopJob j = hop_job(g, 0, i, e.T64.all(), e.RH.all(), d0, lcs, 0.25);
@@ -428,7 +438,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         layout(*t);
         if (!t->host.empty()) t->upload(st);
     }
-    for (auto* t : {&Nb, &Bp, &InitFirst, &InitRel, &InitRestart, &Acc, &SW, &SXR, &SS}) {
+    for (auto* t : {&Nb, &Bp, &InitFirst, &InitRel, &InitRestart, &Acc, &Odd, &SW, &SXR, &SS}) {
         layout(*t);
         if (!t->host.empty()) t->upload(st);
     }
@@ -465,10 +475,12 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         // |b_prec - M_prec x_e| < tol (1/(2 kappa)) |b| is |b - M x| < tol |b| (the odd residual vanishes)
         sys.h[i].target2 = P.tol * P.tol * e.a * e.a * e.src.bb;
         sys.h[i].status = ST_RUNNING;
-        if (e.src.bb == 0.0) {  // zero source: x = 0
+        if (e.src.bb == 0.0) {  // zero source: x = 0 (also when a start vector was given)
             e.done = true;
             e.rr_true = 0;
             sys.h[i].status = ST_CONVERGED;
+            WD_CHECK_HIP(hipMemsetAsync(e.X64.base(), 0, e.X64.mem->bytes, st));
+            WD_CHECK_HIP(hipMemsetAsync(e.T64.base(), 0, e.T64.mem->bytes, st));
         }
     }
     sys.upload(st);
@@ -610,7 +622,25 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     // ---- finish: odd half from eq. eo3, unpack. With x_o from eq. eo3 the full residual is
     // b - M x = (b_prec - M_prec x_e) / a on the even sites and exactly zero on the odd ones, so
     // the last FP64 residual gives the true relative residual without another operator pass.
-    run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hrec, sys.d(), 0, st, hop_bytes(Hrec, SF64, L64, 1));
+    // Systems whose last step was an FP64 residual update reuse its D_oe x_e (T64; zero for a zero
+    // source); any other system applies the hop once more.
+    {
+        std::vector<int> by_sweep, by_hop;
+        for (int i = 0; i < n; i++) (S[i].reliable > 0 || S[i].src.bb == 0.0 ? by_sweep : by_hop).push_back(i);
+        if (!by_sweep.empty()) {
+            if ((int)by_sweep.size() == n) run_sweep(OP_AXPY, SF64, Odd, sys.d(), 0, st, sweep_bytes(Odd, 3 * 192));
+            else {
+                auto O = subset(Odd, by_sweep);
+                run_sweep(OP_AXPY, SF64, O, sys.d(), 0, st, sweep_bytes(O, 3 * 192));
+                WD_CHECK_HIP(hipStreamSynchronize(st));
+            }
+        }
+        if (!by_hop.empty()) {
+            auto R = subset(Hrec, by_hop);
+            run_hop(SF64, L64, false, RED_NONE, FIN_STORE, R, sys.d(), 0, st, hop_bytes(R, SF64, L64, 1));
+            WD_CHECK_HIP(hipStreamSynchronize(st));
+        }
+    }
     for (auto& e : S)
         WD_CHECK_HIP(launch_unpack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st));
     sys.download(st);

@@ -282,6 +282,9 @@ def test_error_codes():
         wd.bicgstab_solve(g, 0.125, b, p=wd.params(tol=1e-12, max_iter=1))
     z, stz = wd.bicgstab_solve(g, 0.125, torch.zeros_like(b))
     assert stz["status"] == 0 and float(torch.abs(z).max()) == 0.0
+    # a zero source with a non-zero start vector still gives x = 0
+    z, stz = wd.bicgstab_solve(g, 0.125, torch.zeros_like(b), x=b.clone(), p=wd.params(use_x0=True))
+    assert stz["status"] == 0 and float(torch.abs(z).max()) == 0.0
     with pytest.raises(wd.WdError):
         wd.bicgstab_solve(g, -1.0, b)
     g.close()
