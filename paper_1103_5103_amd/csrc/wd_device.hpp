@@ -22,6 +22,9 @@
 
 namespace wd {
 
+// threads (= sites) per block of the site-parallel kernels
+constexpr int BLOCK_SITES = 256;
+
 // ---------------------------------------------------------------- formats
 enum SpinorFmt { SF64 = 0, SF32 = 1, SF16 = 2 };
 enum LinkFmt { L64_18 = 0, L64_12 = 1, L32_12 = 2, L16_12 = 3, LB16_12 = 4, L32_18 = 5, NLINKFMT = 6 };
@@ -202,6 +205,61 @@ __device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const c
     }
 }
 
+// ---------------------------------------------------------------- LDS staging of input sites
+// A hop block covers BLOCK consecutive checkerboard sites, i.e. whole rows of constant (y, z, t)
+// when Xh divides BLOCK. Its x neighbours lie in the same rows and its y neighbours one row up
+// or down, so the block first copies the input sites [cb0 - H, cb0 + BLOCK + H) with H = Xh
+// (when Xh <= STG_H_MAX) into LDS with aligned, coalesced loads, and the four x and y
+// directions then read LDS instead of gathering from memory. Neighbours outside that window
+// (the periodic wrap in y, or H = 0) are loaded from memory as before.
+constexpr int STG_H_MAX = 32;
+constexpr int STG_SLOTS = BLOCK_SITES + 2 * STG_H_MAX;
+template <int SF, bool ON> struct Stg {
+    int unused;
+};
+template <> struct Stg<SF32, true> {
+    f4v c[6][STG_SLOTS];
+};
+template <> struct Stg<SF16, true> {
+    h8 c[3][STG_SLOTS];
+    float n[STG_SLOTS];
+};
+
+// copy input site i into slot k
+template <int SF>
+__device__ __forceinline__ void stage_site(Stg<SF, true>& L, int k, const SpinorRef& r, long i)
+{
+    if constexpr (SF == SF32) {
+#pragma unroll
+        for (int j = 0; j < 6; j++) L.c[j][k] = gld<f4v>(r.p, chunk_at(6, r.cs, i, j));
+    } else {
+        L.n[k] = gld<float>(r.nrm, i);
+#pragma unroll
+        for (int j = 0; j < 3; j++) L.c[j][k] = gld<h8>(r.p, chunk_at(3, r.cs, i, j));
+    }
+}
+
+template <int SF, class T>
+__device__ __forceinline__ void load_spinor_stg(const Stg<SF, true>& L, int k, cx<T> v[12])
+{
+    if constexpr (SF == SF32) {
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            const f4v q = L.c[j][k];
+            v[2 * j] = mk<T>((T)q[0], (T)q[1]);
+            v[2 * j + 1] = mk<T>((T)q[2], (T)q[3]);
+        }
+    } else {
+        const float n = L.n[k];
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const h8 q = L.c[j][k];
+#pragma unroll
+            for (int m = 0; m < 4; m++) v[4 * j + m] = mk<T>((T)((float)q[2 * m] * n), (T)((float)q[2 * m + 1] * n));
+        }
+    }
+}
+
 // ---------------------------------------------------------------- streaming loads
 // Links are read exactly once per hop: non-temporal loads keep them from evicting the neighbour
 // spinors that other sites of the same XCD are about to re-read from L2.
@@ -350,7 +408,7 @@ __device__ __forceinline__ void store_link(void* base, long lcs, int k, long i, 
 }
 
 // ---------------------------------------------------------------- reductions
-constexpr int BLOCK = 256;
+constexpr int BLOCK = BLOCK_SITES;
 constexpr int NRED = 4;
 
 __device__ __forceinline__ double wave_sum(double v)

@@ -10,6 +10,8 @@
 //  * k_grad    : link derivative of Re<eta, M^{-1} b> (outer products of projected spinors).
 #include "wd_kernels.hpp"
 
+#include <cstdlib>
+
 // Occupancy hints of the hop kernel (minimum waves per SIMD; 0 lets the compiler choose) and
 // the XCD-aware block order, selectable at build time.
 #ifndef WD_HOP_WAVES_LO
@@ -31,6 +33,20 @@
 #endif
 
 namespace wd {
+
+#ifndef WD_HOP_STAGE
+#define WD_HOP_STAGE 1
+#endif
+// LDS staging of the x and y neighbours in the low-precision hop: build default WD_HOP_STAGE,
+// overridden by the environment variable of the same name (0 or 1) for comparisons.
+int hop_stage_default()
+{
+    static const int v = [] {
+        const char* e = std::getenv("WD_HOP_STAGE");
+        return e ? (std::atoi(e) != 0) : WD_HOP_STAGE;
+    }();
+    return v;
+}
 
 // MI355X has 8 XCDs, each with its own L2; consecutive workgroups go to consecutive XCDs. This
 // bijection on [0, nb) hands each XCD one contiguous eighth of the blocks, so the neighbour
@@ -201,8 +217,17 @@ template <> struct Proj<1> { static constexpr int E = 2, F = 0, I1 = 0, I2 = 1; 
 template <> struct Proj<2> { static constexpr int E = 3, F = 1, I1 = 1, I2 = 0; };
 template <> struct Proj<3> { static constexpr int E = 0, F = 0, I1 = 1, I2 = 0; };
 
-template <int MU, int D, bool DAG, int SFI, class T>
-__device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int z, int t, const SpinorRef& in,
+// Where a hop reads its input sites: memory, or (STG) an LDS copy of the window [base, base + nsl)
+// of input sites for the x and y directions.
+template <int SF, bool STG>
+struct HopIn {
+    const SpinorRef& in;
+    const Stg<SF, STG>& L;
+    int base, nsl;
+};
+
+template <int MU, int D, bool DAG, int SFI, bool STG, class T>
+__device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int z, int t, const HopIn<SFI, STG>& in,
                                         const cx<T> W[9], cx<T> acc[12], int dep)
 {
     int xx = x, yy = y, zz = z, tt = t;
@@ -213,7 +238,13 @@ __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int 
     const int nb = cb_index(g, xx, yy, zz, tt) + dep;
 
     cx<T> psi[12];
-    load_spinor<SFI, T>(in, nb, psi);
+    if constexpr (STG && MU < 2) {
+        const int k = nb - in.base;
+        if ((unsigned)k < (unsigned)in.nsl) load_spinor_stg<SFI, T>(in.L, k, psi);
+        else load_spinor<SFI, T>(in.in, nb, psi);
+    } else {
+        load_spinor<SFI, T>(in.in, nb, psi);
+    }
     constexpr bool minus = (D == 0) != DAG;  // projector 1 - gamma
     constexpr int E = Proj<MU>::E + (minus ? 0 : 2);
     constexpr int F = Proj<MU>::F + (minus ? 0 : 2);
@@ -272,21 +303,21 @@ __device__ __forceinline__ void group_barrier(cx<T> acc[12], int& dep)
 
 // Both directions of axis MU; the two links are loaded together (one 16-byte load per chunk for
 // the paired 16-bit formats). G = directions per ordering group.
-template <int MU, int G, bool DAG, int SFI, int LF, class T>
-__device__ __forceinline__ void hop_axis(const Geo& g, int cb, int x, int y, int z, int t, const SpinorRef& in,
+template <int MU, int G, bool DAG, int SFI, int LF, bool STG, class T>
+__device__ __forceinline__ void hop_axis(const Geo& g, int cb, int x, int y, int z, int t, const HopIn<SFI, STG>& in,
                                          const void* links, long lcs, cx<T> acc[12], int& dep)
 {
     cx<T> Wf[9], Wb[9];
     load_link_pair<LF, T>(links, lcs, MU, cb + dep, Wf, Wb);
-    hop_dir<MU, 0, DAG, SFI, T>(g, cb, x, y, z, t, in, Wf, acc, dep);
+    hop_dir<MU, 0, DAG, SFI, STG, T>(g, cb, x, y, z, t, in, Wf, acc, dep);
     group_barrier<2 * MU, G>(acc, dep);
-    hop_dir<MU, 1, DAG, SFI, T>(g, cb, x, y, z, t, in, Wb, acc, dep);
+    hop_dir<MU, 1, DAG, SFI, STG, T>(g, cb, x, y, z, t, in, Wb, acc, dep);
     group_barrier<2 * MU + 1, G>(acc, dep);
 }
 
-template <bool DAG, int SFI, int LF, class T>
-__device__ __forceinline__ void hop_site(const Geo& g, int p, int cb, const SpinorRef& in, const void* links, long lcs,
-                                         cx<T> acc[12])
+template <bool DAG, int SFI, int LF, bool STG, class T>
+__device__ __forceinline__ void hop_site(const Geo& g, int p, int cb, const HopIn<SFI, STG>& in, const void* links,
+                                         long lcs, cx<T> acc[12])
 {
     constexpr int G = HopGroup<SFI>::G;
     int x, y, z, t;
@@ -294,10 +325,10 @@ __device__ __forceinline__ void hop_site(const Geo& g, int p, int cb, const Spin
 #pragma unroll
     for (int k = 0; k < 12; k++) acc[k] = mk<T>(T(0), T(0));
     int dep = 0;
-    hop_axis<0, G, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    hop_axis<1, G, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    hop_axis<2, G, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    hop_axis<3, G, DAG, SFI, LF, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    hop_axis<0, G, DAG, SFI, LF, STG, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    hop_axis<1, G, DAG, SFI, LF, STG, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    hop_axis<2, G, DAG, SFI, LF, STG, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    hop_axis<3, G, DAG, SFI, LF, STG, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
 }
 
 template <int SF> struct HopWaves { static constexpr int W = WD_HOP_WAVES_LO; };
@@ -318,22 +349,43 @@ __device__ __forceinline__ int tiled_block(const HopJob& J, int lb)
     return q + J.bpp * ((zg * J.tz + zz) + J.g.Z * t);
 }
 
-template <int SF, int LF, bool DAG, int RED, int FIN>
+template <int SF, int LF, bool DAG, int RED, int FIN, bool STG>
 __global__ __launch_bounds__(BLOCK, HopWaves<SF>::W > 0 ? HopWaves<SF>::W : 1) void k_hop(
     const HopJob* __restrict__ jobs, int njobs, SysState* __restrict__ sys, int gated, int* exec)
 {
     using T = typename SReal<SF>::T;
     const int b = WD_XCD_REMAP ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
-    const HopJob& J = jobs[find_job(jobs, njobs, b)];
+    int jx = find_job(jobs, njobs, b);
+    int lb = b - jobs[jx].blk0;
+    if (jobs[jx].ilv > 1) {
+        // interleaved group: find_job returned its last job
+        const int K = jobs[jx].ilv;
+        jx = jx - jobs[jx].ilv_pos + lb % K;
+        lb /= K;
+    }
+    const HopJob& J = jobs[jx];
     SysState* S = sys + J.sys;
     if (gated && S->status != ST_RUNNING) return;
-    const int lb = b - J.blk0;
     if (exec && lb == 0 && threadIdx.x == 0) atomicAdd(exec, 1);  // timing: jobs that did work
-    const int cb = tiled_block(J, lb) * BLOCK + threadIdx.x;
+    const int cb0 = tiled_block(J, lb) * BLOCK;
+    const int cb = cb0 + threadIdx.x;
+    __shared__ Stg<SF, STG> stg;
+    int base = 0, nsl = 0;
+    if constexpr (STG) {
+        const int H = J.g.Xh <= STG_H_MAX ? J.g.Xh : 0;
+        base = cb0 - H;
+        nsl = BLOCK + 2 * H;
+        for (int k = threadIdx.x; k < nsl; k += BLOCK) {
+            const int i = base + k;
+            if (i >= 0 && i < J.g.Vh) stage_site<SF>(stg, k, J.in, i);
+        }
+        __syncthreads();
+    }
+    const HopIn<SF, STG> hin{J.in, stg, base, nsl};
     double v[NRED] = {0.0, 0.0, 0.0, 0.0};
     if (cb < J.g.Vh) {
         cx<T> acc[12];
-        hop_site<DAG, SF, LF, T>(J.g, J.parity, cb, J.in, J.links, J.lcs, acc);
+        hop_site<DAG, SF, LF, STG, T>(J.g, J.parity, cb, hin, J.links, J.lcs, acc);
         const T c2 = (T)J.c2;
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[k] = c2 * acc[k];
@@ -847,8 +899,12 @@ static inline dim3 grid1(long nblk) { return dim3((unsigned)nblk); }
 
 #define HOP_CASE(SF_, LF_, DAG_, RED_, FIN_)                                                                        \
     if (sf == SF_ && lf == LF_ && dag == DAG_ && red == RED_ && fin == FIN_) {                                     \
-        hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs,    \
-                           sys, gated, exec);                                                                     \
+        if (SF_ != SF64 && stage)                                                                                  \
+            hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, SF_ != SF64>), grid1(nblocks), dim3(BLOCK), 0, s, \
+                               jobs, njobs, sys, gated, exec);                                                    \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, false>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, \
+                               njobs, sys, gated, exec);                                                          \
         return hipGetLastError();                                                                                  \
     }
 #define HOP_REDS(SF_, LF_, DAG_)                                                                                   \
@@ -876,9 +932,10 @@ hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState
 }
 
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
-                      SysState* sys, int gated, hipStream_t s, int* exec)
+                      SysState* sys, int gated, hipStream_t s, int* exec, int stage)
 {
     if (nblocks <= 0) return hipSuccess;
+    if (stage < 0) stage = hop_stage_default();
     HOP_REDS(SF64, L64_18, false)
     HOP_CASE(SF64, L64_18, true, RED_NONE, FIN_STORE)
     HOP_REDS(SF64, L64_12, false)

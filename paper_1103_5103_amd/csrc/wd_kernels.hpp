@@ -8,9 +8,11 @@ enum HopRed { RED_NONE = 0, RED_ZDOT = 1, RED_OUTX = 2, RED_NORM = 3 };
 enum SweepOp { OP_W = 0, OP_XR = 1, OP_S = 2, OP_SHIFT = 3, OP_INIT = 4, OP_ACC = 5, OP_NORM = 6, OP_MSINIT = 7, OP_AXPY = 8,
                OP_LINCOMB = 9 };
 
-// exec (may be NULL): incremented once per job that was not gated off
+// exec (may be NULL): incremented once per job that was not gated off. stage: LDS staging of the
+// x/y neighbours in the FP32/FP16 hop (1 on, 0 off, -1 the default of hop_stage_default()).
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
-                      SysState* sys, int gated, hipStream_t s, int* exec = nullptr);
+                      SysState* sys, int gated, hipStream_t s, int* exec = nullptr, int stage = -1);
+int hop_stage_default();
 hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState* sys, int gated, hipStream_t s);
 hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long nblocks, SysState* sys, int gated,
                         hipStream_t s, int* exec = nullptr);

@@ -153,6 +153,9 @@ static char* stage_alloc(size_t n)
     return p;
 }
 
+static int job_blocks_factor(const HopJob& j) { return j.ilv > 1 ? j.ilv : 1; }
+static int job_blocks_factor(const SweepJob&) { return 1; }
+
 template <class J>
 void JobTable<J>::upload(hipStream_t s)
 {
@@ -171,7 +174,7 @@ void JobTable<J>::upload(hipStream_t s)
     std::memcpy(stage + off, fin.data(), fin.size() * sizeof(FinJob));
     WD_CHECK_HIP(hipMemcpyAsync(dev->p, stage, n, hipMemcpyHostToDevice, s));
     nblocks = 0;
-    for (auto& j : host) nblocks = std::max<long>(nblocks, (long)j.blk0 + j.nblk);
+    for (auto& j : host) nblocks = std::max<long>(nblocks, (long)j.blk0 + (long)j.nblk * job_blocks_factor(j));
 }
 template struct JobTable<HopJob>;
 template struct JobTable<SweepJob>;

@@ -190,17 +190,52 @@ static HopJob hop_job(const Geo& g, int parity, int sys, const SpinorRef& in, co
     return j;
 }
 
-// Assign block ranges; jobs with the same sys form one reduction group.
+// Interleaved block order for hop jobs that share their links (on by default; the environment
+// variable WD_HOP_ILV=0 turns it off for comparisons).
+static bool interleave_on()
+{
+    static const bool v = [] {
+        const char* e = std::getenv("WD_HOP_ILV");
+        return e ? std::atoi(e) != 0 : true;
+    }();
+    return v;
+}
+
+static bool same_links(const HopJob& a, const HopJob& b)
+{
+    return a.links == b.links && a.parity == b.parity && a.g.Vh == b.g.Vh && a.g.X == b.g.X && a.g.Y == b.g.Y &&
+           a.g.Z == b.g.Z && a.g.T == b.g.T && a.nblk == b.nblk && a.tz == b.tz && a.bpp == b.bpp;
+}
+static bool same_links(const SweepJob&, const SweepJob&) { return false; }
+static void set_group(HopJob& j, int k, int pos)
+{
+    j.ilv = k;
+    j.ilv_pos = pos;
+}
+static void set_group(SweepJob&, int, int) {}
+
+// Assign block ranges; jobs with the same sys form one reduction group. Consecutive hop jobs
+// that read the same links form an interleaved group (at most 64 jobs).
 template <class J>
 static void layout(JobTable<J>& t)
 {
     int b = 0;
     std::map<int, int> group;
-    for (auto& j : t.host) {
-        j.blk0 = b;
-        b += j.nblk;
-        j.rblk0 = group[j.sys];
-        group[j.sys] += j.nblk;
+    const size_t n = t.host.size();
+    for (size_t i = 0; i < n;) {
+        size_t k = i + 1;
+        if (interleave_on())
+            while (k < n && k - i < 64 && same_links(t.host[i], t.host[k])) k++;
+        const int K = (int)(k - i);
+        for (size_t m = i; m < k; m++) {
+            J& j = t.host[m];
+            j.blk0 = b;
+            set_group(j, K, (int)(m - i));
+            j.rblk0 = group[j.sys];
+            group[j.sys] += j.nblk;
+        }
+        b += K * t.host[i].nblk;
+        i = k;
     }
     for (auto& j : t.host) j.rnblk = group[j.sys];
     t.nblocks = b;
@@ -216,11 +251,15 @@ static SweepJob sweep_job(int sys, long n)
     return j;
 }
 
+// Compulsory bytes of a hop launch: every job's spinors; the links once per interleaved group.
 static double hop_bytes(const JobTable<HopJob>& t, int sf, int lf, int extra_fields)
 {
-    double n = 0;
-    for (auto& j : t.host) n += (double)j.g.Vh;
-    return n * (2 * spinor_site_bytes(sf) + link_site_bytes(lf) + extra_fields * spinor_site_bytes(sf));
+    double n = 0, nl = 0;
+    for (auto& j : t.host) {
+        n += (double)j.g.Vh;
+        if (j.ilv <= 1 || j.ilv_pos == 0) nl += (double)j.g.Vh;
+    }
+    return n * (2 + extra_fields) * spinor_site_bytes(sf) + nl * link_site_bytes(lf);
 }
 static double sweep_bytes(const JobTable<SweepJob>& t, double per_site)
 {

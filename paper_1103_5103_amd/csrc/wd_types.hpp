@@ -90,6 +90,12 @@ struct HopJob {
     double c0, c1, c2;   // out = c0 x0 + c1 x1 + c2 * hop
     int tz;              // block order: 0 = site order; > 0 = t fastest within groups of tz z-planes
     int bpp;             // blocks per (z, t) plane when tz > 0
+    // Jobs that read the same links (same gauge field and parity) may form an interleaved group
+    // of ilv consecutive jobs with equal blk0: block blk0 + ilv * l + k runs block l of job
+    // (first + k), so the systems' blocks for one range of sites run together on one XCD and the
+    // links come from memory once and from L2 for the others.
+    int ilv;             // jobs in the group (1: not interleaved)
+    int ilv_pos;         // position of this job in its group
 };
 
 // Roles of the fields of a sweep job

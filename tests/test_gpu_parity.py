@@ -117,7 +117,11 @@ def test_bicgstab_eo_fp64(dims):
 
 
 @pytest.mark.parametrize("spinor,links", [("f32", "f16"), ("f32", "bf16"), ("f32", "f32"), ("f16", "f16")])
-@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 4, 4, 10)])
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 4, 4, 10),
+                                  # rows of X/2 sites: 36 (wider than the LDS halo), 32 (the widest
+                                  # halo), 8 with 32 rows per plane (a block is one whole plane, so
+                                  # the periodic y wrap stays inside the staged window)
+                                  (72, 4, 4, 4), (64, 4, 2, 4), (16, 32, 4, 4)])
 def test_bicgstab_eo_mixed(dims, spinor, links):
     U = li.random_links(dims, 1.0, 1005)
     b = li.gaussian_field(dims, 2005)
