@@ -4,15 +4,19 @@ One step is one pass of the whole hot path over the 32^3x64 workload: the sequen
 single-mass even-odd mixed-precision BiCGstab for all 8 masses (FP16 12-real links, FP32 spinors,
 FP64 reductions and reliable updates, polynomial start guess, heaviest mass first), the same
 single-mass systems solved as one batch (all masses iterating together), and the FP64 BiCGstab-M
-solve of the same 8 masses on the full lattice, all to relative residual 1e-8. Inputs are synthetic: near-Haar random SU(3) links exp(i H) and one complex Gaussian source,
-seeded; they stand in for the paper's quenched ensemble, which is not available.
+solve of the same 8 masses on the full lattice, all to relative residual 1e-8. Inputs are
+synthetic: near-Haar random SU(3) links exp(i H) and one complex Gaussian source, seeded; they
+stand in for the paper's quenched ensemble, which is not available.
 
-The reported value is the low-precision dslash (even-odd hop) throughput: algorithmic bytes of
-every hop launch divided by their durations, measured with HIP events on the launch stream during
-a second pass over the same steps (per-kernel events slow small solves, so the solve wall times and
-ms_per_step come from the first, uninstrumented pass). Per output site a hop moves the input spinor, the output spinor and 8 links
-(96 + 96 + 8 x 24 = 384 B with FP32 spinors and FP16 12-real links) plus the epilogue fields it
-reads. The CPU baseline is the plain FP64 oracle on the host cores.
+The reported value is the throughput of the low-precision dslash (even-odd hop) of the
+single-mass solves: algorithmic bytes of every hop launch of the sequential solves divided by
+their durations, measured with HIP events on the launch stream. Per output site a hop moves the
+input spinor, the output spinor and 8 links (96 + 96 + 8 x 24 = 384 B with FP32 spinors and FP16
+12-real links) plus the epilogue fields it reads. Per-kernel events slow small solves, so the
+solve wall times and ms_per_step come from a first, uninstrumented pass over the steps; a second
+pass runs each method on its own with the events on. The batched solve's hop reads the links once
+for all systems of a launch (they share the gauge field), so its compulsory bytes count the links
+once; it is reported separately. The CPU baseline is the plain FP64 oracle on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 32x64|16x32] [--no-cpu]
 """
@@ -185,16 +189,26 @@ def main():
         log(f"step {i}: mixed sequential {r[0]:.4f}s, mixed batched {r[4]:.4f}s, FP64 BiCGstab-M {r[1]:.4f}s")
     torch.cuda.synchronize()
     t_end = time.perf_counter()
-    # timed region 2: the same steps with every kernel bracketed by HIP events on its stream
-    wd.timing_reset()
-    wd.timing_enable(True)
-    for i in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    hop_ms, hop_n, hop_bytes = wd.timing_get(0)
-    f64_ms, f64_n, f64_bytes = wd.timing_get(1)
-    sw_ms, sw_n, sw_bytes = wd.timing_get(2)
-    wd.timing_enable(False)
+    # timed region 2: each method on its own, every kernel bracketed by HIP events on its stream
+    def instrumented(fn):
+        wd.timing_reset()
+        wd.timing_enable(True)
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        r = [wd.timing_get(c) for c in range(4)]
+        wd.timing_enable(False)
+        return r
+
+    seq = instrumented(lambda: wd.wd_multimass_solve(g, kappas, bd, method=wd.WD_METHOD_SEQUENTIAL,
+                                                     guess=wd.WD_GUESS_POLY, xs=xs, p=p_mixed))
+    bat = instrumented(lambda: wd.wd_multimass_solve(g, kappas, bd, method=wd.WD_METHOD_BATCHED, xs=xb, p=p_mixed))
+    msh = instrumented(lambda: wd.bicgstab_m_solve(g, kappas, bd, xs=xm, p=p_f64))
+    hop_ms, hop_n, hop_bytes = seq[0]
+
+    def gbs(rec):
+        ms, n, by = rec
+        return round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 else None
 
     hop_gbs = hop_bytes / (hop_ms * 1e-3) / 1e9 if hop_ms > 0 else 0.0
     ms_per_step = (t_end - t_start) / args.steps * 1e3
@@ -236,8 +250,12 @@ def main():
         "hop_launches": hop_n,
         "hop_avg_us": round(hop_ms / max(hop_n, 1) * 1e3, 2),
         "hop_bytes_per_launch": round(hop_bytes / max(hop_n, 1)),
-        "fp64_hop_GBps": round(f64_bytes / (f64_ms * 1e-3) / 1e9, 1) if f64_ms > 0 else None,
-        "sweep_GBps": round(sw_bytes / (sw_ms * 1e-3) / 1e9, 1) if sw_ms > 0 else None,
+        "kernels_GBps": {
+            "sequential": {"lo_hop": gbs(seq[0]), "fp64_hop": gbs(seq[1]), "sweeps": gbs(seq[2])},
+            "batched": {"lo_hop_links_shared": gbs(bat[0]), "fp64_hop_links_shared": gbs(bat[1]),
+                        "sweeps": gbs(bat[2]), "lo_hop_avg_us": round(bat[0][0] / max(bat[0][1], 1) * 1e3, 1)},
+            "multishift": {"fp64_hop": gbs(msh[1]), "sweeps": gbs(msh[2])},
+        },
         "solve_s_mixed_sequential": round(t_mixed, 5),
         "solve_s_mixed_batched": round(t_b, 5),
         "solve_s_fp64_multishift": round(t_ms, 5),

@@ -224,6 +224,7 @@ struct HopIn {
     const SpinorRef& in;
     const Stg<SF, STG>& L;
     int base, nsl;
+    bool nt;  // non-temporal link loads (links not shared with other systems of the launch)
 };
 
 template <int MU, int D, bool DAG, int SFI, bool STG, class T>
@@ -308,7 +309,8 @@ __device__ __forceinline__ void hop_axis(const Geo& g, int cb, int x, int y, int
                                          const void* links, long lcs, cx<T> acc[12], int& dep)
 {
     cx<T> Wf[9], Wb[9];
-    load_link_pair<LF, T>(links, lcs, MU, cb + dep, Wf, Wb);
+    if (in.nt) load_link_pair<LF, T, true>(links, lcs, MU, cb + dep, Wf, Wb);
+    else load_link_pair<LF, T, false>(links, lcs, MU, cb + dep, Wf, Wb);
     hop_dir<MU, 0, DAG, SFI, STG, T>(g, cb, x, y, z, t, in, Wf, acc, dep);
     group_barrier<2 * MU, G>(acc, dep);
     hop_dir<MU, 1, DAG, SFI, STG, T>(g, cb, x, y, z, t, in, Wb, acc, dep);
@@ -381,7 +383,7 @@ __global__ __launch_bounds__(BLOCK, HopWaves<SF>::W > 0 ? HopWaves<SF>::W : 1) v
         }
         __syncthreads();
     }
-    const HopIn<SF, STG> hin{J.in, stg, base, nsl};
+    const HopIn<SF, STG> hin{J.in, stg, base, nsl, J.ilv <= 1};
     double v[NRED] = {0.0, 0.0, 0.0, 0.0};
     if (cb < J.g.Vh) {
         cx<T> acc[12];
