@@ -77,6 +77,12 @@ typedef struct {
     double delta_reliable; /* mixed: reliable update once |r| < delta * max|r| since the last one     */
     int use_x0;            /* 1: x holds the start vector on entry (single-mass solves only)          */
     int dagger;            /* 1: solve M^dag x = b instead, through M^dag = gamma5 M gamma5            */
+    int mixed_mode;        /* mixed only. WD_MIXED_RELIABLE: one Krylov run; x and r are refreshed in
+                              FP64 once |r| < delta * max|r| since the last refresh, keeping the
+                              shadow vector and search direction. WD_MIXED_DEFECT: defect correction
+                              (Sec. 6.2.4): each inner low-precision solve of M e = r runs until |r|
+                              drops below delta times its starting value, then x += e and r = b - M x
+                              are updated in FP64 and a fresh inner solve starts                       */
 } wd_solver_params;
 
 typedef struct {
@@ -96,9 +102,10 @@ typedef struct {
 
 enum { WD_METHOD_SEQUENTIAL = 0, WD_METHOD_MULTISHIFT = 1, WD_METHOD_BATCHED = 2 };
 enum { WD_GUESS_NONE = 0, WD_GUESS_POLY = 1 };
+enum { WD_MIXED_RELIABLE = 0, WD_MIXED_DEFECT = 1 };
 
 /* Defaults: tol 1e-8, max_iter 5000, mixed 1, F32 spinors, F16 links, recon 12, eo 1,
-   delta_reliable 0.1, use_x0 0, dagger 0. */
+   delta_reliable 0.1, use_x0 0, dagger 0, mixed_mode WD_MIXED_RELIABLE. */
 void wd_params_default(wd_solver_params* p);
 
 /*

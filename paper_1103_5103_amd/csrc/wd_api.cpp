@@ -55,6 +55,8 @@ static void check_params(const wd_solver_params* p)
             throw Error{WD_ERR_UNSUPPORTED, "spinor_store must be WD_F64, WD_F32 or WD_F16"};
         (void)link_fmt_of(p->link_store, p->recon);
         if (!(p->delta_reliable > 0 && p->delta_reliable < 1)) throw Error{WD_ERR_ARG, "delta_reliable must be in (0,1)"};
+        if (p->mixed_mode != WD_MIXED_RELIABLE && p->mixed_mode != WD_MIXED_DEFECT)
+            throw Error{WD_ERR_ARG, "mixed_mode must be WD_MIXED_RELIABLE or WD_MIXED_DEFECT"};
     }
 }
 
@@ -74,6 +76,7 @@ void wd_params_default(wd_solver_params* p)
     p->delta_reliable = 0.1;
     p->use_x0 = 0;
     p->dagger = 0;
+    p->mixed_mode = WD_MIXED_RELIABLE;
 }
 
 const char* wd_status_str(wd_status s)

@@ -123,7 +123,7 @@ __device__ void finish(SysState* S, const double* tot)
         else if (S->iter >= S->maxit) pend = ST_MAXIT;
         else if (c_abs2(d1) == 0.0) pend = ST_BREAKDOWN;
         S->pending = pend;
-        if (rr > S->maxrr) S->maxrr = rr;
+        if (!S->dc && rr > S->maxrr) S->maxrr = rr;
         for (int i = 0; i < S->nshift; i++) {
             ShiftScal& q = S->sh[i];
             if (!q.active) continue;

@@ -359,6 +359,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         q.maxit = P.max_iter;
         q.mixed = P.mixed;
         q.delta_rel2 = P.delta_reliable * P.delta_reliable;
+        q.dc = P.mixed && P.mixed_mode == WD_MIXED_DEFECT;
         q.target2 = -1.0;
         q.status = ST_RUNNING;
     }
@@ -642,7 +643,12 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
                 active--;
             }
         }
-        // new residual: keep rhat and s (reliable update) or restart with rhat = s = r (breakdown)
+        // new residual: keep rhat and s (reliable update) or restart with rhat = s = r (breakdown,
+        // and every outer step of defect correction: a fresh inner solve of M e = r)
+        if (P.mixed && P.mixed_mode == WD_MIXED_DEFECT) {
+            restart.insert(restart.end(), cont.begin(), cont.end());
+            cont.clear();
+        }
         if (!cont.empty()) {
             if ((int)cont.size() == n) run_sweep(OP_INIT, SFL, InitRel, sys.d(), 0, st, 0);
             else {
@@ -652,9 +658,13 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
             }
         }
         if (!restart.empty()) {
-            auto I = subset(InitRestart, restart);
-            run_sweep(OP_INIT, SFL, I, sys.d(), 0, st, 0);
-            WD_CHECK_HIP(hipStreamSynchronize(st));
+            if ((int)restart.size() == n) run_sweep(OP_INIT, SFL, InitRestart, sys.d(), 0, st, 0);
+            else {
+                std::sort(restart.begin(), restart.end());
+                auto I = subset(InitRestart, restart);
+                run_sweep(OP_INIT, SFL, I, sys.d(), 0, st, 0);
+                WD_CHECK_HIP(hipStreamSynchronize(st));
+            }
         }
     }
 

@@ -54,7 +54,8 @@ struct SysState {
     int mixed;
     int rsel;          // which residual buffer holds r_n (multi-shift keeps r_n and r_{n+1})
     int nshift;
-    int pad;
+    int dc;            // defect correction: the reliable-update threshold is relative to the
+                       // residual at the start of the inner solve (maxrr is not raised)
     double2 delta, beta, chi, alpha, beta_prev;
     double rr;         // |r|^2 of the iterated residual
     double maxrr;      // max |r|^2 since the last reliable update

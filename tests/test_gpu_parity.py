@@ -136,6 +136,46 @@ def test_bicgstab_eo_mixed(dims, spinor, links):
     g.close()
 
 
+@pytest.mark.parametrize("spinor", ["f32", "f16"])
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (16, 32, 4, 4)])
+def test_bicgstab_eo_defect_correction(dims, spinor):
+    """The paper's mixed-precision scheme (Sec. 6.2.4): restarted inner low-precision solves, each
+    to a lower tolerance, with FP64 updates of x and r between them; the oracle's operator gives
+    the true residual."""
+    U = li.random_links(dims, 1.0, 1005)
+    b = li.gaussian_field(dims, 2005)
+    g = wd.wd_gauge_create(_t(U))
+    kappa = 0.13
+    x, st = wd.bicgstab_solve(g, kappa, _t(b), p=wd.params(tol=1e-8, spinor=spinor, links="f16", delta=1e-2,
+                                                             defect_correction=True))
+    res = oracle.true_residual(U, kappa, _n(x), b)
+    _say("eo defect correction", dims, spinor, st, "oracle residual", res)
+    assert st["status"] == 0
+    assert res < 1e-8
+    # each inner solve gains at most about two orders beyond delta: several outer steps are needed
+    assert st["reliable_updates"] >= 2
+    assert abs(st["true_rel_res"] - res) < 1e-2 * res
+    g.close()
+
+
+def test_defect_correction_multimass_batched():
+    """Defect correction for all masses of one source, sequential (with the polynomial guess) and
+    batched, every mass to 1e-8 by the oracle's operator."""
+    dims = (8, 8, 8, 16)
+    U = li.random_links(dims, 1.0, 1011)
+    b = li.gaussian_field(dims, 2011)
+    kappas = [0.120, 0.124, 0.128, 0.132]
+    g = wd.wd_gauge_create(_t(U))
+    p = wd.params(tol=1e-8, spinor="f32", links="f16", delta=1e-3, defect_correction=True)
+    for method in (wd.WD_METHOD_SEQUENTIAL, wd.WD_METHOD_BATCHED):
+        xs, sts = wd.wd_multimass_solve(g, kappas, _t(b), method=method, p=p)
+        for k, x, s in zip(kappas, xs, sts):
+            res = oracle.true_residual(U, k, _n(x), b)
+            _say("defect correction multimass", method, k, s, res)
+            assert s["status"] == 0 and res < 1e-8
+    g.close()
+
+
 def test_bicgstab_dagger_solves_adjoint():
     dims = (4, 4, 4, 8)
     U = li.random_links(dims, 1.0, 1006)
