@@ -84,18 +84,34 @@ struct Timer {
 Timer& timer();
 
 // ---------------------------------------------------------------- job tables
-template <class J>
-struct JobTable {
-    std::vector<J> host;
+// A launch's job list (and the list of systems its finisher reduces) in device memory. A table
+// owns its device copy (upload), or several tables share one buffer and one copy (upload_tables).
+struct JobTableBase {
     std::shared_ptr<DevMem> dev;
-    std::vector<FinJob> fin;  // one entry per system, for the finisher kernel
+    size_t off = 0;  // byte offset of this table in dev
+    size_t cap = 0;  // bytes reserved for this table at off
     long nblocks = 0;
+    virtual ~JobTableBase() = default;
+    virtual size_t prepare() = 0;          // finisher list, nblocks; returns the image size
+    virtual void write(char* dst) const = 0;  // the image: jobs, then the finisher list
+};
+
+template <class J>
+struct JobTable : JobTableBase {
+    std::vector<J> host;
+    std::vector<FinJob> fin;  // one entry per system, for the finisher kernel
     void upload(hipStream_t s);
+    size_t prepare() override;
+    void write(char* dst) const override;
     int n() const { return (int)host.size(); }
-    const J* d() const { return (const J*)dev->p; }
-    const FinJob* fin_d() const { return (const FinJob*)((const char*)dev->p + fin_offset()); }
+    const J* d() const { return (const J*)((const char*)dev->p + off); }
+    const FinJob* fin_d() const { return (const FinJob*)((const char*)dev->p + off + fin_offset()); }
     size_t fin_offset() const { return (host.size() * sizeof(J) + 255) / 256 * 256; }
 };
+
+// Upload several non-empty tables with one host-to-device copy into mem (grown when too small;
+// tables still holding the previous buffer keep it alive).
+void upload_tables(hipStream_t s, std::shared_ptr<DevMem>& mem, std::initializer_list<JobTableBase*> tables);
 
 // ---------------------------------------------------------------- gauge handle
 } // namespace wd

@@ -157,7 +157,7 @@ static int job_blocks_factor(const HopJob& j) { return j.ilv > 1 ? j.ilv : 1; }
 static int job_blocks_factor(const SweepJob&) { return 1; }
 
 template <class J>
-void JobTable<J>::upload(hipStream_t s)
+size_t JobTable<J>::prepare()
 {
     // finisher list: the systems of this launch in order of first appearance
     fin.clear();
@@ -166,15 +166,54 @@ void JobTable<J>::upload(hipStream_t s)
         for (auto& f : fin) seen = seen || f.sys == j.sys;
         if (!seen) fin.push_back(FinJob{j.sys, j.rnblk});
     }
-    const size_t off = fin_offset();
-    size_t n = off + fin.size() * sizeof(FinJob);
-    if (!dev || dev->bytes < n) dev = std::make_shared<DevMem>(std::max(n, sizeof(J)));
-    char* stage = stage_alloc(n);
-    std::memcpy(stage, host.data(), host.size() * sizeof(J));
-    std::memcpy(stage + off, fin.data(), fin.size() * sizeof(FinJob));
-    WD_CHECK_HIP(hipMemcpyAsync(dev->p, stage, n, hipMemcpyHostToDevice, s));
     nblocks = 0;
     for (auto& j : host) nblocks = std::max<long>(nblocks, (long)j.blk0 + (long)j.nblk * job_blocks_factor(j));
+    return (fin_offset() + fin.size() * sizeof(FinJob) + 255) / 256 * 256;
+}
+
+template <class J>
+void JobTable<J>::write(char* dst) const
+{
+    std::memcpy(dst, host.data(), host.size() * sizeof(J));
+    std::memcpy(dst + fin_offset(), fin.data(), fin.size() * sizeof(FinJob));
+}
+
+template <class J>
+void JobTable<J>::upload(hipStream_t s)
+{
+    // in place when the table's slot is large enough (also inside a buffer shared with other
+    // tables), else into a buffer of its own
+    const size_t n = prepare();
+    if (!dev || n > cap) {
+        dev = std::make_shared<DevMem>(std::max(n, sizeof(J)));
+        off = 0;
+        cap = std::max(n, sizeof(J));
+    }
+    char* stage = stage_alloc(n);
+    write(stage);
+    WD_CHECK_HIP(hipMemcpyAsync((char*)dev->p + off, stage, n, hipMemcpyHostToDevice, s));
+}
+
+void upload_tables(hipStream_t s, std::shared_ptr<DevMem>& mem, std::initializer_list<JobTableBase*> tables)
+{
+    size_t total = 0;
+    std::vector<size_t> offs;
+    for (JobTableBase* t : tables) {
+        offs.push_back(total);
+        total += t->prepare();
+    }
+    if (total == 0) return;
+    if (!mem || mem->bytes < total) mem = std::make_shared<DevMem>(total);
+    char* stage = stage_alloc(total);
+    size_t k = 0;
+    for (JobTableBase* t : tables) {
+        t->write(stage + offs[k]);
+        t->dev = mem;
+        t->off = offs[k];
+        t->cap = (k + 1 < offs.size() ? offs[k + 1] : total) - offs[k];
+        k++;
+    }
+    WD_CHECK_HIP(hipMemcpyAsync(mem->p, stage, total, hipMemcpyHostToDevice, s));
 }
 template struct JobTable<HopJob>;
 template struct JobTable<SweepJob>;

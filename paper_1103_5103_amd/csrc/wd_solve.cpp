@@ -67,10 +67,12 @@ static double link_site_bytes(int lf) { return 8.0 * link_chunks(lf) * link_chun
 struct SysArray {
     std::shared_ptr<DevMem> dev;
     std::vector<SysState> h;
-    void alloc(int n)
+    // cache: a buffer kept by a gauge handle across solves (grown when too small)
+    void alloc(int n, std::shared_ptr<DevMem>& cache)
     {
         h.assign(n, SysState{});
-        dev = std::make_shared<DevMem>(sizeof(SysState) * n);
+        if (!cache || cache->bytes < sizeof(SysState) * n) cache = std::make_shared<DevMem>(sizeof(SysState) * n);
+        dev = cache;
     }
     SysState* d() const { return (SysState*)dev->p; }
     void upload(hipStream_t s)
@@ -349,7 +351,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     }
 
     SysArray sys;
-    sys.alloc(n);
+    sys.alloc(n, S[0].g->raw["eo.sys"]);
     for (int i = 0; i < n; i++) {
         EoSys& e = S[i];
         SysState& q = sys.h[i];
@@ -474,14 +476,12 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         for (auto& j : t->host) set_tile(j, tile_64[j.sys]);
     for (auto* t : {&H1, &H2, &H3, &H4})
         for (auto& j : t->host) set_tile(j, tile_lo[j.sys]);
-    for (auto* t : {&Hhb, &Hx1, &Hx2, &Hrec, &H1, &H2, &H3, &H4}) {
-        layout(*t);
-        if (!t->host.empty()) t->upload(st);
-    }
-    for (auto* t : {&Nb, &Bp, &InitFirst, &InitRel, &InitRestart, &Acc, &Odd, &SW, &SXR, &SS}) {
-        layout(*t);
-        if (!t->host.empty()) t->upload(st);
-    }
+    for (auto* t : {&Hhb, &Hx1, &Hx2, &Hrec, &H1, &H2, &H3, &H4}) layout(*t);
+    for (auto* t : {&Nb, &Bp, &InitFirst, &InitRel, &InitRestart, &Acc, &Odd, &SW, &SXR, &SS}) layout(*t);
+    // one copy for all tables, into a buffer kept by the first handle across solves
+    upload_tables(st, S[0].g->raw["eo.tables"],
+                  {&Hhb, &Hx1, &Hx2, &Hrec, &H1, &H2, &H3, &H4, &Nb, &Bp, &InitFirst, &InitRel, &InitRestart, &Acc,
+                   &Odd, &SW, &SXR, &SS});
 
     // ---- setup
     if (!need_src.empty()) {
@@ -733,7 +733,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
     const int L64 = g->f64_links();
 
     SysArray sys;
-    sys.alloc(1);
+    sys.alloc(1, g->raw["ms.sys"]);
     SysState& q = sys.h[0];
     std::memset(&q, 0, sizeof(q));
     q.partials = (double*)g->rawbuf("ms.partials", sizeof(double) * NRED * (2 * geo.stride / BLOCK + 1));
@@ -813,16 +813,12 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
         h.c0 = a;
         HAw.host.push_back(h);
     }
-    for (auto* t : {&Init, &SW, &SXR, &SEND}) {
-        layout(*t);
-        t->upload(st);
-    }
     const int tz64 = tune_tile(g, SF64, L64, st);
-    for (auto* t : {&HAs, &HAw}) {
+    for (auto* t : {&HAs, &HAw})
         for (auto& h : t->host) set_tile(h, tz64);
-        layout(*t);
-        t->upload(st);
-    }
+    for (auto* t : {&Init, &SW, &SXR, &SEND}) layout(*t);
+    for (auto* t : {&HAs, &HAw}) layout(*t);
+    upload_tables(st, g->raw["ms.tables"], {&Init, &SW, &SXR, &SEND, &HAs, &HAw});
     run_sweep(OP_MSINIT, SF64, Init, sys.d(), 0, st, 0);
     sys.download(st);
     const double bb = sys.h[0].red[2];
@@ -1083,9 +1079,9 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
                 sj.flags = (m7 << 8) | (j0 > 0 ? 1 : 0);
                 L.host.push_back(sj);
                 layout(L);
-                L.upload(st);
+                // stream order: the copy runs after the previous chunk's sweep has read the buffer
+                upload_tables(st, g->raw["mm.tables"], {&L});
                 run_sweep(OP_LINCOMB, SF64, L, dummy, 0, st, sweep_bytes(L, (m7 + 1 + (j0 > 0)) * 192.0));
-                WD_CHECK_HIP(hipStreamSynchronize(st));
             }
             e.x_ready = true;
         }
