@@ -123,6 +123,10 @@ __device__ void finish(SysState* S, const double* tot)
         else if (S->iter >= S->maxit) pend = ST_MAXIT;
         else if (c_abs2(d1) == 0.0) pend = ST_BREAKDOWN;
         S->pending = pend;
+        // no shifted scalars to rotate: commit now instead of in a separate end-of-iteration
+        // finisher. The s update of this iteration is then gated off for a system that stops;
+        // a solver that continues from s (reliable update) applies it before the update.
+        if (S->nshift == 0) S->status = pend;
         if (!S->dc && rr > S->maxrr) S->maxrr = rr;
         for (int i = 0; i < S->nshift; i++) {
             ShiftScal& q = S->sh[i];

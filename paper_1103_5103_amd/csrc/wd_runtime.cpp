@@ -274,8 +274,7 @@ void run_sweep(int op, int sfl, const JobTable<SweepJob>& t, SysState* sys, int 
     }
     switch (op) {
     case OP_XR: run_finish(3, FIN_ALPHA, t, sys, gated, s); break;
-    case OP_S:
-    case OP_SHIFT: run_finish(0, FIN_END, t, sys, gated, s); break;
+    case OP_SHIFT: run_finish(0, FIN_END, t, sys, gated, s); break;  // OP_S: committed in FIN_ALPHA
     case OP_INIT:
     case OP_MSINIT: run_finish(3, FIN_RESTART, t, sys, gated, s); break;
     case OP_NORM: run_finish(3, FIN_STORE, t, sys, gated, s); break;

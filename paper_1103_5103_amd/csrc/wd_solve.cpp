@@ -559,6 +559,17 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     };
     // reliable update for a subset: x_hi += x_lo, r_hi = b_prec - M_prec x_hi, |r_hi|^2
     auto reliable_update = [&](const std::vector<int>& ids) {
+        // the s update of the iteration in which the system stopped was gated off: apply it
+        // (the scalars of that iteration are still in place), since a continuing reliable update
+        // keeps s; defect correction restarts with s = r instead
+        if (!(P.mixed && P.mixed_mode == WD_MIXED_DEFECT)) {
+            if ((int)ids.size() == n) run_sweep(OP_S, SFL, SS, sys.d(), 0, st, bSS);
+            else {
+                auto T = subset(SS, ids);
+                run_sweep(OP_S, SFL, T, sys.d(), 0, st, sweep_bytes(T, 4 * bl));
+                WD_CHECK_HIP(hipStreamSynchronize(st));
+            }
+        }
         if ((int)ids.size() == n) {
             run_sweep(OP_ACC, SFL, Acc, sys.d(), 0, st, sweep_bytes(Acc, 2 * 192 + 2 * bx));
             run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hx1, sys.d(), 0, st, hop_bytes(Hx1, SF64, L64, 0));
