@@ -213,6 +213,18 @@ def main():
                                          xs=xd, p=p_dc)
         torch.cuda.synchronize()
         t_dc.append(time.perf_counter() - a)
+    # gain of the start guesses against their order (Sec. 7, Fig. 6): total iterations of the
+    # sequential solve over the zero-guess baseline, for the Lagrange and the solution-space
+    # minimisation guesses using the k most recent solutions, k = 1 .. n-1
+    def total_iters(guess, order):
+        p = wd.params(tol=1e-8, spinor=W["spinor"], links=W["links"], delta=W["delta"], guess_order=order)
+        _, sts = wd.wd_multimass_solve(g, kappas, bd, method=wd.WD_METHOD_SEQUENTIAL, guess=guess, xs=xd, p=p)
+        return sum(s["iters"] for s in sts)
+
+    base_iters = total_iters(wd.WD_GUESS_NONE, 0)
+    gain = {"baseline_iters": base_iters,
+            "poly": [round(total_iters(wd.WD_GUESS_POLY, k) / base_iters, 3) for k in range(1, len(kappas))],
+            "minres": [round(total_iters(wd.WD_GUESS_MINRES, k) / base_iters, 3) for k in range(1, len(kappas))]}
     seq = instrumented(lambda: wd.wd_multimass_solve(g, kappas, bd, method=wd.WD_METHOD_SEQUENTIAL,
                                                      guess=wd.WD_GUESS_POLY, xs=xs, p=p_mixed))
     bat = instrumented(lambda: wd.wd_multimass_solve(g, kappas, bd, method=wd.WD_METHOD_BATCHED, xs=xb, p=p_mixed))
@@ -281,6 +293,7 @@ def main():
             "outer_updates": [s["reliable_updates"] for s in st_dc],
             "true_rel_res": [float(f"{s['true_rel_res']:.3e}") for s in st_dc],
         },
+        "guess_gain_vs_order": gain,
         "iters_mixed": [s["iters"] for s in st_mixed],
         "iters_batched": [s["iters"] for s in st_b],
         "true_rel_res_batched": [float(f"{s['true_rel_res']:.3e}") for s in st_b],

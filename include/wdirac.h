@@ -83,6 +83,8 @@ typedef struct {
                               (Sec. 6.2.4): each inner low-precision solve of M e = r runs until |r|
                               drops below delta times its starting value, then x += e and r = b - M x
                               are updated in FP64 and a fresh inner solve starts                       */
+    int guess_order;       /* sequential multi-mass start guesses use at most this many previous
+                              solutions, the most recently solved ones (0: all of them)               */
 } wd_solver_params;
 
 typedef struct {
@@ -101,11 +103,11 @@ typedef struct {
 } wd_system;
 
 enum { WD_METHOD_SEQUENTIAL = 0, WD_METHOD_MULTISHIFT = 1, WD_METHOD_BATCHED = 2 };
-enum { WD_GUESS_NONE = 0, WD_GUESS_POLY = 1 };
+enum { WD_GUESS_NONE = 0, WD_GUESS_POLY = 1, WD_GUESS_MINRES = 2 };
 enum { WD_MIXED_RELIABLE = 0, WD_MIXED_DEFECT = 1 };
 
 /* Defaults: tol 1e-8, max_iter 5000, mixed 1, F32 spinors, F16 links, recon 12, eo 1,
-   delta_reliable 0.1, use_x0 0, dagger 0, mixed_mode WD_MIXED_RELIABLE. */
+   delta_reliable 0.1, use_x0 0, dagger 0, mixed_mode WD_MIXED_RELIABLE, guess_order 0. */
 void wd_params_default(wd_solver_params* p);
 
 /*
@@ -128,9 +130,9 @@ wd_status wd_apply_dag(wd_gauge* g, double kappa, double* out, const double* in,
  * Single-mass BiCGstab for M(kappa) x = b (van der Vorst's method, cited in Sec. 6; the solution
  * update x <- x - beta s + chi w of Sec. 5). With params->eo the even-odd system of Sec. 6.2.3
  * (eq. eo2-eo4) is solved and the odd half rebuilt from eq. eo3. With params->mixed the
- * iteration runs with low-precision storage and FP64 reliable updates, which recompute the true
- * residual inside one Krylov run instead of restarting an inner solve as the paper's
- * defect-correction scheme does (Sec. 6.2.4).
+ * iteration runs with low-precision storage and FP64 updates of x and r: reliable updates inside
+ * one Krylov run, or the paper's defect correction with restarted inner solves (Sec. 6.2.4),
+ * selected by params->mixed_mode.
  * x, b: device [V][3][4] complex128. stats (may be NULL): filled on return, also on NOCONV.
  * Returns WD_OK, WD_ERR_NOCONV (x holds the last iterate), WD_ERR_BREAKDOWN, WD_ERR_NAN, ...
  */
@@ -151,7 +153,11 @@ wd_status bicgstab_m_solve(wd_gauge* g, int n, const double* kappas, double* con
 /*
  * Multi-mass driver (Sec. 6, eq. 6.1; Sec. 7). method WD_METHOD_SEQUENTIAL: single-mass BiCGstab
  * once per mass, heaviest mass (smallest kappa) first; with WD_GUESS_POLY each start vector is the
- * highest-order Lagrange extrapolation in m a of the solutions found so far (Sec. 6.2.1).
+ * highest-order Lagrange extrapolation in m a of the solutions found so far (Sec. 6.2.1); with
+ * WD_GUESS_MINRES it is the combination of those solutions that minimises |b - M(kappa) v|_2
+ * (solution-space minimisation, Sec. 6.2.2: since M(kappa) psi_k = b + (1/(2 kappa) -
+ * 1/(2 kappa_k)) psi_k, the normal equations need inner products of the stored solutions only, no
+ * operator application). params->guess_order limits either guess to the most recent solutions.
  * method WD_METHOD_MULTISHIFT: one bicgstab_m_solve. method WD_METHOD_BATCHED: the single-mass
  * systems of all masses iterate together (one kernel launch per solver step for all of them,
  * converged masses drop out, even-odd required); no start guesses. 1 <= n <= 32.

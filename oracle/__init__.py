@@ -210,24 +210,43 @@ def poly_weights(m_prev, m_new):
     return c
 
 
-def multimass_sequential(U, kappas, b, tol=1e-10, maxit=10000, guess="poly", eo=True, antiperiodic=True):
+def solution_space_guess(b, psis, kappas_prev, kappa):
+    """Solution-space minimisation (Sec. 6.2.2): the combination v = sum_j c_j psi_j of earlier
+    solutions psi_j (of M(kappa_j) psi_j = b) that minimises |b - M(kappa) v|_2. Because the
+    masses enter M only through the diagonal, M(kappa) psi_j = b + (m - m_j) a psi_j with
+    (m - m_j) a = 1/(2 kappa) - 1/(2 kappa_j), so no operator is applied: the columns
+    d_j = b + s_j psi_j go to a plain least-squares solve. Returns (v, c)."""
+    b = _c128(b).reshape(-1)
+    cols = [b + (1.0 / (2.0 * kappa) - 1.0 / (2.0 * kj)) * _c128(p).reshape(-1) for p, kj in zip(psis, kappas_prev)]
+    D = np.stack(cols, axis=1)
+    c = np.linalg.lstsq(D, b, rcond=None)[0]
+    v = sum(cj * _c128(p) for cj, p in zip(c, psis))
+    return v, c
+
+
+def multimass_sequential(U, kappas, b, tol=1e-10, maxit=10000, guess="poly", eo=True, antiperiodic=True, order=0):
     """Single-mass BiCGstab once per mass, heaviest mass (smallest kappa) first; with
-    guess='poly' each start vector is the highest-order Lagrange extrapolation in m a of the
-    solutions found so far (Sec. 6.2.1, Sec. 7). Returns (solutions in the caller's order,
-    iteration counts in the caller's order)."""
-    order = sorted(range(len(kappas)), key=lambda i: kappas[i])
+    guess='poly' each start vector is the Lagrange extrapolation in m a of the solutions found so
+    far (Sec. 6.2.1, Sec. 7), with guess='minres' their residual-minimising combination (Sec.
+    6.2.2); order > 0 uses only the most recent `order` solutions. Returns (solutions in the
+    caller's order, iteration counts in the caller's order)."""
+    seq = sorted(range(len(kappas)), key=lambda i: kappas[i])
     sols, its = [None] * len(kappas), [0] * len(kappas)
-    done_m, done_x = [], []
-    for i in order:
+    done_m, done_x, done_k = [], [], []
+    for i in seq:
         x0 = None
         m = float(mass_of_kappa(kappas[i]))
-        if guess == "poly" and done_x:
-            c = poly_weights(done_m, m)
-            x0 = sum(cj * xj for cj, xj in zip(c, done_x))
+        k = len(done_x) if order <= 0 else min(order, len(done_x))
+        if guess == "poly" and k:
+            c = poly_weights(done_m[-k:], m)
+            x0 = sum(cj * xj for cj, xj in zip(c, done_x[-k:]))
+        elif guess == "minres" and k:
+            x0, _ = solution_space_guess(b, done_x[-k:], done_k[-k:], kappas[i])
         x, it, st, _ = bicgstab(U, kappas[i], b, tol, maxit, x0=x0, antiperiodic=antiperiodic, eo=eo)
         sols[i], its[i] = x, it
         done_m.append(m)
         done_x.append(x)
+        done_k.append(kappas[i])
     return sols, its
 
 

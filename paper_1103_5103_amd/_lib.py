@@ -22,7 +22,7 @@ LIBPATH = os.path.join(_HERE, "libwdirac.so")
 WD_OK, WD_ERR_ARG, WD_ERR_HIP, WD_ERR_OOM, WD_ERR_NOCONV, WD_ERR_BREAKDOWN, WD_ERR_NAN, WD_ERR_UNSUPPORTED = range(8)
 WD_F64, WD_F32, WD_F16, WD_BF16 = range(4)
 WD_METHOD_SEQUENTIAL, WD_METHOD_MULTISHIFT, WD_METHOD_BATCHED = 0, 1, 2
-WD_GUESS_NONE, WD_GUESS_POLY = 0, 1
+WD_GUESS_NONE, WD_GUESS_POLY, WD_GUESS_MINRES = 0, 1, 2
 WD_MIXED_RELIABLE, WD_MIXED_DEFECT = 0, 1
 PREC = {"f64": WD_F64, "f32": WD_F32, "f16": WD_F16, "bf16": WD_BF16}
 
@@ -44,6 +44,7 @@ class SolverParams(ctypes.Structure):
         ("use_x0", ctypes.c_int),
         ("dagger", ctypes.c_int),
         ("mixed_mode", ctypes.c_int),
+        ("guess_order", ctypes.c_int),
     ]
 
 
@@ -156,13 +157,14 @@ def _ptr(t: torch.Tensor, name: str, shape=None):
 
 
 def params(tol=1e-8, max_iter=5000, mixed=True, spinor="f32", links="f16", recon=12, eo=True, delta=0.1,
-           use_x0=False, dagger=False, defect_correction=False) -> SolverParams:
+           use_x0=False, dagger=False, defect_correction=False, guess_order=0) -> SolverParams:
     p = SolverParams()
     load().wd_params_default(ctypes.byref(p))
     p.tol, p.max_iter, p.mixed = float(tol), int(max_iter), int(bool(mixed))
     p.spinor_store, p.link_store, p.recon = PREC[spinor], PREC[links], int(recon)
     p.eo, p.delta_reliable, p.use_x0, p.dagger = int(bool(eo)), float(delta), int(bool(use_x0)), int(bool(dagger))
     p.mixed_mode = WD_MIXED_DEFECT if defect_correction else WD_MIXED_RELIABLE
+    p.guess_order = int(guess_order)
     return p
 
 

@@ -618,7 +618,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
             store_spinor<SF64, double>(J.f[R_F0], i, a);
         }
     } else if constexpr (OP == OP_LINCOMB) {
-        // f0 (+)= sum_{j < m} c_j f_{1+j}, m = flags >> 8 (<= 7); flags & 1: accumulate into f0
+        // f0 (+)= sum_{j < m} c_j f_{1+j}, m = flags >> 8; flags & 1: accumulate into f0;
+        // flags & 2: complex c_j = (c[2j], c[2j+1]) (m <= 4), else real c_j = c[j] (m <= 7)
         if (ok) {
             cx<double> acc[12], a[12];
             if (J.flags & 1) load_spinor<SF64, double>(J.f[R_F0], i, acc);
@@ -627,10 +628,12 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
                 for (int k = 0; k < 12; k++) acc[k] = mk<double>(0.0, 0.0);
             }
             const int m = J.flags >> 8;
+            const bool cplx = (J.flags & 2) != 0;
             for (int j = 0; j < m; j++) {
                 load_spinor<SF64, double>(J.f[1 + j], i, a);
+                const cx<double> cj = cplx ? mk<double>(J.c[2 * j], J.c[2 * j + 1]) : mk<double>(J.c[j], 0.0);
 #pragma unroll
-                for (int k = 0; k < 12; k++) acc[k] = acc[k] + J.c[j] * a[k];
+                for (int k = 0; k < 12; k++) acc[k] = acc[k] + cj * a[k];
             }
             store_spinor<SF64, double>(J.f[R_F0], i, acc);
         }
@@ -657,6 +660,65 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
             }
         }
         write_partials<3>(v, S, J.rblk0 + lb);
+    }
+}
+
+// ================================================================ inner products of full fields
+
+// <a, b_j> for j < m (m <= DOTS_MAX) over the real sites of two full FP64 fields in the internal
+// layout (padding sites of each half skipped). Block partials [block][2 m], then one block sums
+// them in a fixed order: deterministic.
+__global__ __launch_bounds__(BLOCK) void k_dots(SpinorRef a, const SpinorRef* __restrict__ bs, int m, int Vh,
+                                                int stride, double* __restrict__ partials)
+{
+    __shared__ double lds[BLOCK / 64];
+    const long i = (long)blockIdx.x * BLOCK + threadIdx.x;  // site of the full field, [0, 2 stride)
+    const bool ok = i < 2L * stride && (i % stride) < Vh;
+    cx<double> va[12];
+    if (ok) load_spinor<SF64, double>(a, i, va);
+    for (int j = 0; j < m; j++) {
+        double re = 0.0, im = 0.0;
+        if (ok) {
+            cx<double> vb[12];
+            load_spinor<SF64, double>(bs[j], i, vb);
+#pragma unroll
+            for (int k = 0; k < 12; k++) {
+                re += va[k].re * vb[k].re + va[k].im * vb[k].im;
+                im += va[k].re * vb[k].im - va[k].im * vb[k].re;
+            }
+        }
+        double v[2] = {re, im};
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            double s = wave_sum(v[c]);
+            if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double t = 0.0;
+                for (int w = 0; w < BLOCK / 64; w++) t += lds[w];
+                partials[(long)blockIdx.x * 2 * DOTS_MAX + 2 * j + c] = t;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_dots_finish(const double* __restrict__ partials, int nblk, int m,
+                                                       double* __restrict__ out)
+{
+    __shared__ double lds[BLOCK / 64];
+    for (int c = 0; c < 2 * m; c++) {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += BLOCK) t += partials[(long)b * 2 * DOTS_MAX + c];
+        t = wave_sum(t);
+        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double u = 0.0;
+            for (int w = 0; w < BLOCK / 64; w++) u += lds[w];
+            out[c] = u;
+        }
+        __syncthreads();
     }
 }
 
@@ -1015,6 +1077,18 @@ hipError_t launch_convert_links(int lf, const void* src, void* dst, int Vh, long
     case LB16_12: hipLaunchKernelGGL((k_convert_links<LB16_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_dots(SpinorRef a, const SpinorRef* bs, int m, const Geo& g, double* partials, double* out,
+                       hipStream_t s)
+{
+    if (m < 1 || m > DOTS_MAX) return hipErrorInvalidValue;
+    const int nb = (int)((2L * g.stride + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL(k_dots, grid1(nb), dim3(BLOCK), 0, s, a, bs, m, g.Vh, g.stride, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dots_finish, dim3(1), dim3(BLOCK), 0, s, partials, nb, m, out);
     return hipGetLastError();
 }
 

@@ -23,6 +23,11 @@ hipError_t launch_unpack_spinor(int sf, double* dst, const Geo& g, SpinorRef eve
 hipError_t launch_pack_links(const double* U, const Geo& g, void* even, void* odd, long lcs, hipStream_t s);
 hipError_t launch_convert_links(int lf, const void* src, void* dst, int Vh, long lcs, hipStream_t s);
 hipError_t launch_recon_check(const void* lk, int Vh, long lcs, double* blockmax, hipStream_t s);
+// out[2 j], out[2 j + 1] = <a, bs[j]> (j < m <= DOTS_MAX) over the real sites of full FP64 fields;
+// bs: device array of m views; partials: device, >= (2 stride / BLOCK + 1) * 2 * DOTS_MAX doubles
+constexpr int DOTS_MAX = 8;
+hipError_t launch_dots(SpinorRef a, const SpinorRef* bs, int m, const Geo& g, double* partials, double* out,
+                       hipStream_t s);
 hipError_t launch_lincomb(double* out, const double* const* ins, const double* c, int k, long ncomplex, hipStream_t s);
 hipError_t launch_grad(const double* x, const double* lam, const Geo& g, const void* lk_even, const void* lk_odd,
                        long lcs, double* out, int project, hipStream_t s);

@@ -990,6 +990,88 @@ wd_status solve_batch(int nsys, const wd_system* sys, const wd_solver_params& P,
     return worst;
 }
 
+// <a, v_j> for every view v_j (full FP64 fields of handle g), through the device multi-dot
+static std::vector<double2> field_dots(wd_gauge* g, const SpinorRef& a, const std::vector<SpinorRef>& vs,
+                                       hipStream_t st)
+{
+    std::vector<double2> out;
+    const Geo& G = g->geo;
+    double* partials = (double*)g->rawbuf("dots.partials", sizeof(double) * 2 * DOTS_MAX * (2 * G.stride / BLOCK + 1));
+    SpinorRef* refs = (SpinorRef*)g->rawbuf("dots.refs", sizeof(SpinorRef) * DOTS_MAX);
+    double* res = (double*)g->rawbuf("dots.out", sizeof(double) * 2 * DOTS_MAX);
+    for (size_t j0 = 0; j0 < vs.size(); j0 += DOTS_MAX) {
+        const int m = (int)std::min<size_t>(DOTS_MAX, vs.size() - j0);
+        char* stg = (char*)pinned(sizeof(SpinorRef) * DOTS_MAX + sizeof(double) * 2 * DOTS_MAX);
+        std::memcpy(stg, vs.data() + j0, sizeof(SpinorRef) * m);
+        WD_CHECK_HIP(hipMemcpyAsync(refs, stg, sizeof(SpinorRef) * m, hipMemcpyHostToDevice, st));
+        WD_CHECK_HIP(launch_dots(a, refs, m, G, partials, res, st));
+        double* back = (double*)(stg + sizeof(SpinorRef) * DOTS_MAX);
+        WD_CHECK_HIP(hipMemcpyAsync(back, res, sizeof(double) * 2 * m, hipMemcpyDeviceToHost, st));
+        WD_CHECK_HIP(hipStreamSynchronize(st));
+        for (int j = 0; j < m; j++) out.push_back(make_double2(back[2 * j], back[2 * j + 1]));
+    }
+    return out;
+}
+
+// Solution-space minimisation (Sec. 6.2.2) for the mass kappa over the solutions done[j_first ..
+// j_first + k): with d_j = M(kappa) psi_j = b + s_j psi_j, s_j = 1/(2 kappa) - 1/(2 kappa_j),
+// minimise |b - sum_j c_j d_j|_2: sum_j <d_i, d_j> c_j = <d_i, b>, with
+//   <d_i, d_j> = |b|^2 + s_j <b, psi_j> + s_i <psi_i, b> + s_i s_j <psi_i, psi_j>.
+// Gaussian elimination with partial pivoting on the small Hermitian system, with a relative
+// 1e-13 diagonal shift against exactly dependent solutions.
+static std::vector<double2> minres_coefficients(const std::vector<std::vector<double2>>& Pg,
+                                                const std::vector<double2>& qb, double bb, const double* kappas,
+                                                const std::vector<int>& done, int j_first, int k, double kappa)
+{
+    auto cmul = [](double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); };
+    auto cdiv = [](double2 a, double2 b) {
+        const double d = b.x * b.x + b.y * b.y;
+        return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+    };
+    std::vector<double> sv(k);
+    for (int j = 0; j < k; j++) sv[j] = 1.0 / (2.0 * kappa) - 1.0 / (2.0 * kappas[done[j_first + j]]);
+    std::vector<std::vector<double2>> A(k, std::vector<double2>(k + 1));
+    double dmax = 0;
+    for (int i = 0; i < k; i++) {
+        const int gi = j_first + i;
+        const double2 qi = qb[gi], qic = make_double2(qi.x, -qi.y);  // <b, psi_i>, <psi_i, b>
+        for (int j = 0; j < k; j++) {
+            const int gj = j_first + j;
+            const double2 qj = qb[gj];
+            const double2 pij = Pg[gi][gj];
+            A[i][j] = make_double2(bb + sv[j] * qj.x + sv[i] * qic.x + sv[i] * sv[j] * pij.x,
+                                   sv[j] * qj.y + sv[i] * qic.y + sv[i] * sv[j] * pij.y);
+        }
+        A[i][k] = make_double2(bb + sv[i] * qic.x, sv[i] * qic.y);
+        dmax = std::max(dmax, A[i][i].x);
+    }
+    for (int i = 0; i < k; i++) A[i][i].x += 1e-13 * dmax;
+    for (int col = 0; col < k; col++) {
+        int piv = col;
+        for (int r = col + 1; r < k; r++)
+            if (std::hypot(A[r][col].x, A[r][col].y) > std::hypot(A[piv][col].x, A[piv][col].y)) piv = r;
+        std::swap(A[col], A[piv]);
+        if (A[col][col].x == 0.0 && A[col][col].y == 0.0) continue;
+        for (int r = col + 1; r < k; r++) {
+            const double2 f = cdiv(A[r][col], A[col][col]);
+            for (int c = col; c <= k; c++) {
+                const double2 t = cmul(f, A[col][c]);
+                A[r][c] = make_double2(A[r][c].x - t.x, A[r][c].y - t.y);
+            }
+        }
+    }
+    std::vector<double2> c(k, make_double2(0, 0));
+    for (int i = k - 1; i >= 0; i--) {
+        double2 t = A[i][k];
+        for (int j = i + 1; j < k; j++) {
+            const double2 u = cmul(A[i][j], c[j]);
+            t = make_double2(t.x - u.x, t.y - u.y);
+        }
+        c[i] = (A[i][i].x == 0.0 && A[i][i].y == 0.0) ? make_double2(0, 0) : cdiv(t, A[i][i]);
+    }
+    return c;
+}
+
 wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* const* x, const double* b, int method,
                           int guess, const wd_solver_params& P, wd_solver_stats* stats, hipStream_t st)
 {
@@ -1000,7 +1082,7 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
         // every mass is its own single-mass system; all iterate together, one launch per solver
         // step, sharing one packed source (no start guesses: the masses are solved simultaneously)
         WD_REQUIRE(P.eo, "batched solves use even-odd preconditioning");
-        WD_REQUIRE(guess == WD_GUESS_NONE || guess == WD_GUESS_POLY, "unknown guess");
+        WD_REQUIRE(guess == WD_GUESS_NONE || guess == WD_GUESS_POLY || guess == WD_GUESS_MINRES, "unknown guess");
         EoSource src;
         prepare_source(g, "mm.", b, P.dagger, src, st);
         std::vector<EoSys> S(n);
@@ -1029,7 +1111,8 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
         return worst;
     }
     WD_REQUIRE(method == WD_METHOD_SEQUENTIAL, "unknown method");
-    WD_REQUIRE(guess == WD_GUESS_NONE || guess == WD_GUESS_POLY, "unknown guess");
+    WD_REQUIRE(guess == WD_GUESS_NONE || guess == WD_GUESS_POLY || guess == WD_GUESS_MINRES, "unknown guess");
+    WD_REQUIRE(P.guess_order >= 0, "guess_order must be >= 0");
     std::vector<int> order(n);
     for (int i = 0; i < n; i++) order[i] = i;
     // heaviest mass (smallest kappa) first (Sec. 7)
@@ -1051,6 +1134,10 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
     for (int i = 0; i < n; i++) X[i] = g->field("mm.X" + std::to_string(i), SF64, 2);
     SysState* dummy = (SysState*)g->rawbuf("apply.sys", sizeof(SysState));
     std::vector<int> done;
+    // solution-space minimisation: Gram entries <psi_i, psi_j> and <b, psi_i> of the solutions in
+    // order of completion (indices into done)
+    std::vector<std::vector<double2>> Pg;
+    std::vector<double2> qb;
     for (int idx : order) {
         wd_solver_params Q = P;
         Q.use_x0 = 0;
@@ -1062,37 +1149,50 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
         e.slot = 0;
         e.src = src;
         e.X64 = X[idx];
-        if (guess == WD_GUESS_POLY && !done.empty()) {
-            // Lagrange weights in m a = 1/(2 kappa) - 4 (Sec. 6.2.1), highest order available
-            const double m = 1.0 / (2.0 * kappas[idx]) - 4.0;
-            const int k = (int)done.size();
-            std::vector<double> c(k);
-            for (int jj = 0; jj < k; jj++) {
-                const double mj = 1.0 / (2.0 * kappas[done[jj]]) - 4.0;
-                double w = 1.0;
-                for (int ii = 0; ii < k; ii++) {
-                    if (ii == jj) continue;
-                    const double mi = 1.0 / (2.0 * kappas[done[ii]]) - 4.0;
-                    w *= (m - mi) / (mj - mi);
+        const int kall = (int)done.size();
+        const int k = P.guess_order > 0 ? std::min(P.guess_order, kall) : kall;
+        const int j_first = kall - k;  // the k most recently solved masses
+        if (guess != WD_GUESS_NONE && k > 0) {
+            std::vector<double2> c(k);
+            if (guess == WD_GUESS_POLY) {
+                // Lagrange weights in m a = 1/(2 kappa) - 4 (Sec. 6.2.1)
+                const double m = 1.0 / (2.0 * kappas[idx]) - 4.0;
+                for (int jj = 0; jj < k; jj++) {
+                    const double mj = 1.0 / (2.0 * kappas[done[j_first + jj]]) - 4.0;
+                    double w = 1.0;
+                    for (int ii = 0; ii < k; ii++) {
+                        if (ii == jj) continue;
+                        const double mi = 1.0 / (2.0 * kappas[done[j_first + ii]]) - 4.0;
+                        w *= (m - mi) / (mj - mi);
+                    }
+                    c[jj] = make_double2(w, 0.0);
                 }
-                c[jj] = w;
+            } else {
+                c = minres_coefficients(Pg, qb, src.bb, kappas, done, j_first, k, kappas[idx]);
             }
-            // x0_e = sum_j c_j x_j,e  in chunks of 7 inputs per sweep
-            for (int j0 = 0; j0 < k; j0 += 7) {
+            // x0 = sum_j c_j x_j over the even half, in chunks (7 real or 4 complex inputs per sweep)
+            const bool cplx = guess == WD_GUESS_MINRES;
+            const int per = cplx ? 4 : 7;
+            for (int j0 = 0; j0 < k; j0 += per) {
                 JobTable<SweepJob> L;
                 SweepJob sj = sweep_job(0, X[idx].stride);
                 sj.f[R_F0] = X[idx].half(0);
-                const int m7 = std::min(7, k - j0);
-                for (int jj = 0; jj < m7; jj++) {
-                    sj.f[1 + jj] = X[done[j0 + jj]].half(0);
-                    sj.c[jj] = c[j0 + jj];
+                const int mc = std::min(per, k - j0);
+                for (int jj = 0; jj < mc; jj++) {
+                    sj.f[1 + jj] = X[done[j_first + j0 + jj]].half(0);
+                    if (cplx) {
+                        sj.c[2 * jj] = c[j0 + jj].x;
+                        sj.c[2 * jj + 1] = c[j0 + jj].y;
+                    } else {
+                        sj.c[jj] = c[j0 + jj].x;
+                    }
                 }
-                sj.flags = (m7 << 8) | (j0 > 0 ? 1 : 0);
+                sj.flags = (mc << 8) | (j0 > 0 ? 1 : 0) | (cplx ? 2 : 0);
                 L.host.push_back(sj);
                 layout(L);
                 // stream order: the copy runs after the previous chunk's sweep has read the buffer
                 upload_tables(st, g->raw["mm.tables"], {&L});
-                run_sweep(OP_LINCOMB, SF64, L, dummy, 0, st, sweep_bytes(L, (m7 + 1 + (j0 > 0)) * 192.0));
+                run_sweep(OP_LINCOMB, SF64, L, dummy, 0, st, sweep_bytes(L, (mc + 1 + (j0 > 0)) * 192.0));
             }
             e.x_ready = true;
         }
@@ -1108,6 +1208,21 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
         }
         if (S[0].final_status != WD_OK && worst == WD_OK) worst = (wd_status)S[0].final_status;
         done.push_back(idx);
+        if (guess == WD_GUESS_MINRES && (int)done.size() < n) {
+            // inner products of the new solution with b and with every stored solution (itself
+            // included), full lattice: <x_new, v> for v in (b, x_done...)
+            std::vector<SpinorRef> vs{src.B64.all()};
+            for (int j : done) vs.push_back(X[j].all());
+            std::vector<double2> d = field_dots(g, X[idx].all(), vs, st);
+            qb.push_back(make_double2(d[0].x, -d[0].y));  // <b, x_new>
+            const int kn = (int)done.size();
+            for (auto& row : Pg) row.push_back(make_double2(0, 0));
+            Pg.emplace_back(kn);
+            for (int j = 0; j < kn; j++) {
+                Pg[kn - 1][j] = d[1 + j];                                   // <x_new, x_j>
+                Pg[j][kn - 1] = make_double2(d[1 + j].x, -d[1 + j].y);      // <x_j, x_new>
+            }
+        }
     }
     return worst;
 }

@@ -292,6 +292,80 @@ def test_multimass_sequential_with_guess():
     assert sum(its) < sum(its0)
 
 
+def _free_plane_wave_solution(dims, kappa, p, u):
+    X, Y, Z, T = dims
+    ma = 1 / (2 * kappa) - 4
+    t, z, y, x = np.meshgrid(np.arange(T), np.arange(Z), np.arange(Y), np.arange(X), indexing="ij")
+    phase = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))
+    K = (ma + sum(1 - np.cos(v) for v in p)) * np.eye(4) + 1j * sum(np.sin(p[m]) * oracle.gamma(m) for m in range(4))
+    return phase[..., None, None] * u, phase[..., None, None] * (u @ np.linalg.inv(K))
+
+
+def test_solution_space_guess_exact_in_free_field():
+    """U = 1 and a plane-wave source: x(m) = e^{ip.n} u (W - iS)/(W^2 + s^2) with S = sum sin(p)
+    gamma, S^2 = s^2, so every solution lies in the two-dimensional span of e^{ip.n} u and
+    e^{ip.n} u S. From the exact solutions at two masses the minimising combination (Sec. 6.2.2)
+    must reproduce the solution at any third mass; the two-point Lagrange guess (linear in m)
+    cannot."""
+    dims = (4, 4, 4, 8)
+    p = [2 * np.pi / 4, 0.0, 2 * np.pi * 3 / 4, 3 * np.pi / 8]
+    u = np.arange(12).reshape(3, 4) + 1j
+    U = li.unit_links(dims)
+    k_prev = [0.110, 0.115]
+    b, _ = _free_plane_wave_solution(dims, 0.11, p, u)
+    psis = [_free_plane_wave_solution(dims, k, p, u)[1] for k in k_prev]
+    for kappa in (0.118, 0.122, 0.105):
+        _, exact = _free_plane_wave_solution(dims, kappa, p, u)
+        v, c = oracle.solution_space_guess(b, psis, k_prev, kappa)
+        assert _rel(v, exact) < 1e-11
+        assert oracle.true_residual(U, kappa, v, b) < 1e-12
+        w = oracle.poly_weights([oracle.mass_of_kappa(k) for k in k_prev], oracle.mass_of_kappa(kappa))
+        vp = sum(wj * pj for wj, pj in zip(w, psis))
+        assert oracle.true_residual(U, kappa, vp, b) > 1e-4
+
+
+def test_solution_space_guess_minimises_over_the_span():
+    """Random links: the columns are M(kappa) psi_j (checked against the operator itself), and no
+    other combination of the same solutions (the Lagrange guess, or each solution alone with its
+    best scale) has a smaller residual."""
+    dims = (4, 4, 4, 8)
+    U = li.random_links(dims, 1.0, 1012)
+    b = li.gaussian_field(dims, 2012)
+    k_prev = [0.120, 0.123, 0.126]
+    psis = [oracle.bicgstab(U, k, b, tol=1e-13)[0] for k in k_prev]
+    kappa = 0.129
+    for k, ps in zip(k_prev, psis):
+        d = b + (1 / (2 * kappa) - 1 / (2 * k)) * ps
+        assert _rel(oracle.apply(U, kappa, ps), d) < 1e-11
+    v, c = oracle.solution_space_guess(b, psis, k_prev, kappa)
+    r_min = np.linalg.norm(b - oracle.apply(U, kappa, v))
+    w = oracle.poly_weights([oracle.mass_of_kappa(k) for k in k_prev], oracle.mass_of_kappa(kappa))
+    vp = sum(wj * pj for wj, pj in zip(w, psis))
+    assert r_min <= np.linalg.norm(b - oracle.apply(U, kappa, vp)) * (1 + 1e-12)
+    for ps in psis:
+        mp = oracle.apply(U, kappa, ps).reshape(-1)
+        alpha = np.vdot(mp, b.reshape(-1)) / np.vdot(mp, mp)
+        assert r_min <= np.linalg.norm(b.reshape(-1) - alpha * mp) * (1 + 1e-12)
+    # the normal equations hold: the residual is orthogonal to every M(kappa) psi_j
+    r = (b - oracle.apply(U, kappa, v)).reshape(-1)
+    for ps in psis:
+        assert abs(np.vdot(oracle.apply(U, kappa, ps).reshape(-1), r)) < 1e-9 * np.linalg.norm(b) ** 2
+
+
+def test_multimass_sequential_minres_guess_and_order():
+    dims = (4, 4, 4, 8)
+    U = li.random_links(dims, 1.0, 1001)
+    b = li.gaussian_field(dims, 2001)
+    kappas = [0.120, 0.122, 0.124, 0.126, 0.128, 0.130]
+    sols0, its0 = oracle.multimass_sequential(U, kappas, b, tol=1e-10, guess="none")
+    for guess in ("minres", "poly"):
+        for order in (0, 1, 2):
+            sols, its = oracle.multimass_sequential(U, kappas, b, tol=1e-10, guess=guess, order=order)
+            for k, x in zip(kappas, sols):
+                assert oracle.true_residual(U, k, x, b) < 2e-10
+            assert sum(its) < sum(its0)
+
+
 # ------------------------------------------------------------------ gradient
 
 def _loss(U, kappa, eta, b):
