@@ -85,6 +85,12 @@ typedef struct {
                               are updated in FP64 and a fresh inner solve starts                       */
     int guess_order;       /* sequential multi-mass start guesses use at most this many previous
                               solutions, the most recently solved ones (0: all of them)               */
+    int temporal_gauge;    /* read by wd_gauge_create only: 1 = the handle's solvers work in temporal
+                              gauge (a bandwidth saving named in Sec. 4): sources are rotated by
+                              g(x,t) = U_t(x,0)...U_t(x,t-1), solutions back by g^dag, and the time
+                              links, then the unit matrix except on the last time slice, are neither
+                              loaded nor multiplied. Only for links that are SU(3) to rounding (else
+                              ignored). Solutions agree with the caller's gauge to rounding.          */
 } wd_solver_params;
 
 typedef struct {
@@ -107,7 +113,8 @@ enum { WD_GUESS_NONE = 0, WD_GUESS_POLY = 1, WD_GUESS_MINRES = 2 };
 enum { WD_MIXED_RELIABLE = 0, WD_MIXED_DEFECT = 1 };
 
 /* Defaults: tol 1e-8, max_iter 5000, mixed 1, F32 spinors, F16 links, recon 12, eo 1,
-   delta_reliable 0.1, use_x0 0, dagger 0, mixed_mode WD_MIXED_RELIABLE, guess_order 0. */
+   delta_reliable 0.1, use_x0 0, dagger 0, mixed_mode WD_MIXED_RELIABLE, guess_order 0,
+   temporal_gauge 0. */
 void wd_params_default(wd_solver_params* p);
 
 /*

@@ -2,6 +2,7 @@
 // converts C++ exceptions into wd_status codes and records a thread-local message.
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -145,9 +146,13 @@ wd_status wd_gauge_create(wd_gauge** out, const wd_geom* geom, const double* U, 
                 for (double v : h) e = std::max(e, std::isfinite(v) ? v : 1.0);
             }
             g->recon_err = e;
-            if (e < 1e-12) g->ensure_links(L64_12, s);
+            const bool tg_on = hint && hint->temporal_gauge;
+            if (e < 1e-12) {
+                if (tg_on) g->build_temporal_gauge(U, s);
+                else g->ensure_links(L64_12, s);
+            }
         }
-        if (hint && hint->mixed) g->ensure_links(link_fmt_of(hint->link_store, hint->recon), s);
+        if (hint && hint->mixed) g->ensure_slinks(link_fmt_of(hint->link_store, hint->recon), s);
         WD_CHECK_HIP(hipStreamSynchronize(s));
         *out = g.release();
         return WD_OK;

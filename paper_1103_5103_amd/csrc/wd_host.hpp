@@ -120,18 +120,29 @@ struct wd_gauge {
     wd::Geo geo;
     long V = 0;
     std::unique_ptr<wd::DevMem> links[wd::NLINKFMT];  // both output parities, [parity][8][chunks][stride]
+    // Solvers work in temporal gauge when the links are SU(3) to rounding: sources are rotated by
+    // g(n) on the way in, solutions by g(n)^dag on the way out, and the solver link formats are
+    // built from the transformed links (links[] keeps the caller's gauge for wd_apply and the
+    // gradient).
+    bool tg = false;
+    std::unique_ptr<wd::DevMem> gmat;                   // g(n), canonical [V][3][3] complex128
+    std::unique_ptr<wd::DevMem> fixed[wd::NLINKFMT];    // transformed links, same layouts
+    const double* gm() const { return tg ? (const double*)gmat->p : nullptr; }
+    const void* slk(int lf, int parity) const;          // links of format lf for the solvers
+    void ensure_slinks(int lf, hipStream_t s);
     std::map<std::string, wd::Field> ws;              // cached workspace fields
     std::map<std::string, std::shared_ptr<wd::DevMem>> raw;
     std::map<std::string, wd::JobTable<wd::HopJob>> hop_tables;
     hipStream_t stream = nullptr;
     double recon_err = 1.0;  // max |row2 - conj(row0 x row1)| over the links
-    // FP64 operator format: 12-real when the links are SU(3) to rounding, else 18-real
+    // FP64 operator format of the solvers: 12-real when the links are SU(3) to rounding, else 18-real
     int f64_links() const { return recon_err < 1e-12 ? wd::L64_12 : wd::L64_18; }
     const void* lk(int lf, int parity) const;
     long lcs() const { return geo.stride; }
     wd::Field& field(const std::string& key, int sf, int halves);
     void* rawbuf(const std::string& key, size_t bytes);
     void ensure_links(int lf, hipStream_t s);
+    void build_temporal_gauge(const double* U, hipStream_t s);  // U: the caller's canonical links
     size_t device_bytes() const;
 };
 

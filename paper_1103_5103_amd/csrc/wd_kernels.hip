@@ -229,11 +229,12 @@ struct HopIn {
     const Stg<SF, STG>& L;
     int base, nsl;
     bool nt;  // non-temporal link loads (links not shared with other systems of the launch)
+    bool tg;  // temporal gauge: unit time links inside the lattice
 };
 
 template <int MU, int D, bool DAG, int SFI, bool STG, class T>
 __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int z, int t, const HopIn<SFI, STG>& in,
-                                        const cx<T> W[9], cx<T> acc[12], int dep)
+                                        const cx<T> W[9], cx<T> acc[12], int dep, bool unit)
 {
     int xx = x, yy = y, zz = z, tt = t;
     if constexpr (MU == 0) xx = D == 0 ? (x + 1 == g.X ? 0 : x + 1) : (x == 0 ? g.X - 1 : x - 1);
@@ -261,10 +262,18 @@ __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int 
         h2[c] = psi[c * 4 + 2] + mul_ik<-F>(psi[c * 4 + I2]);
     }
     cx<T> g1[3], g2[3];
+    if (unit) {
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        g1[a] = W[a * 3] * h1[0] + W[a * 3 + 1] * h1[1] + W[a * 3 + 2] * h1[2];
-        g2[a] = W[a * 3] * h2[0] + W[a * 3 + 1] * h2[1] + W[a * 3 + 2] * h2[2];
+        for (int a = 0; a < 3; a++) {
+            g1[a] = h1[a];
+            g2[a] = h2[a];
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            g1[a] = W[a * 3] * h1[0] + W[a * 3 + 1] * h1[1] + W[a * 3 + 2] * h1[2];
+            g2[a] = W[a * 3] * h2[0] + W[a * 3 + 1] * h2[1] + W[a * 3 + 2] * h2[2];
+        }
     }
     if constexpr (MU == 3) {
         const bool flip = g.anti && (D == 0 ? (t == g.T - 1) : (t == 0));
@@ -313,11 +322,16 @@ __device__ __forceinline__ void hop_axis(const Geo& g, int cb, int x, int y, int
                                          const void* links, long lcs, cx<T> acc[12], int& dep)
 {
     cx<T> Wf[9], Wb[9];
-    if (in.nt) load_link_pair<LF, T, true>(links, lcs, MU, cb + dep, Wf, Wb);
-    else load_link_pair<LF, T, false>(links, lcs, MU, cb + dep, Wf, Wb);
-    hop_dir<MU, 0, DAG, SFI, STG, T>(g, cb, x, y, z, t, in, Wf, acc, dep);
+    // temporal gauge: U_t(n) is the unit matrix unless t = T - 1, U_t(n - t)^dag unless t = 0
+    const bool unit_f = MU == 3 && in.tg && t != g.T - 1;
+    const bool unit_b = MU == 3 && in.tg && t != 0;
+    if (!(unit_f && unit_b)) {
+        if (in.nt) load_link_pair<LF, T, true>(links, lcs, MU, cb + dep, Wf, Wb);
+        else load_link_pair<LF, T, false>(links, lcs, MU, cb + dep, Wf, Wb);
+    }
+    hop_dir<MU, 0, DAG, SFI, STG, T>(g, cb, x, y, z, t, in, Wf, acc, dep, unit_f);
     group_barrier<2 * MU, G>(acc, dep);
-    hop_dir<MU, 1, DAG, SFI, STG, T>(g, cb, x, y, z, t, in, Wb, acc, dep);
+    hop_dir<MU, 1, DAG, SFI, STG, T>(g, cb, x, y, z, t, in, Wb, acc, dep, unit_b);
     group_barrier<2 * MU + 1, G>(acc, dep);
 }
 
@@ -355,7 +369,8 @@ __device__ __forceinline__ int tiled_block(const HopJob& J, int lb)
     return q + J.bpp * ((zg * J.tz + zz) + J.g.Z * t);
 }
 
-template <int SF, int LF, bool DAG, int RED, int FIN, bool STG>
+// TG: some job of the launch has temporal-gauge links (TG = false compiles the unit-link paths out)
+template <int SF, int LF, bool DAG, int RED, int FIN, bool STG, bool TG>
 __global__ __launch_bounds__(BLOCK, HopWaves<SF>::W > 0 ? HopWaves<SF>::W : 1) void k_hop(
     const HopJob* __restrict__ jobs, int njobs, SysState* __restrict__ sys, int gated, int* exec)
 {
@@ -387,7 +402,7 @@ __global__ __launch_bounds__(BLOCK, HopWaves<SF>::W > 0 ? HopWaves<SF>::W : 1) v
         }
         __syncthreads();
     }
-    const HopIn<SF, STG> hin{J.in, stg, base, nsl, J.ilv <= 1};
+    const HopIn<SF, STG> hin{J.in, stg, base, nsl, J.ilv <= 1, TG && J.tg != 0};
     double v[NRED] = {0.0, 0.0, 0.0, 0.0};
     if (cb < J.g.Vh) {
         cx<T> acc[12];
@@ -727,8 +742,10 @@ __global__ __launch_bounds__(BLOCK) void k_dots_finish(const double* __restrict_
 // canonical [V][3][4] complex128 (lexicographic) <-> internal per-parity half fields.
 // gamma5 != 0 multiplies spin components 2 and 3 by -1 on the way (gamma5 = diag(1,1,-1,-1)).
 template <int SF>
+// gm (may be NULL): colour rotation g(n) applied on the way, psi'(n) = g(n) psi(n) (temporal gauge)
 __global__ __launch_bounds__(BLOCK) void k_pack_spinor(const double2* __restrict__ src, Geo g, SpinorRef even,
-                                                       SpinorRef odd, int gamma5, double scale)
+                                                       SpinorRef odd, int gamma5, double scale,
+                                                       const double2* __restrict__ gm)
 {
     const int p = blockIdx.y;
     const int cb = blockIdx.x * BLOCK + threadIdx.x;
@@ -743,12 +760,26 @@ __global__ __launch_bounds__(BLOCK) void k_pack_spinor(const double2* __restrict
         double sg = (gamma5 && (k & 3) >= 2) ? -scale : scale;
         v[k] = mk<double>(sg * q.x, sg * q.y);
     }
+    if (gm) {
+        cx<double> G[9], w[12];
+#pragma unroll
+        for (int k = 0; k < 9; k++) G[k] = mk<double>(gm[n * 9 + k].x, gm[n * 9 + k].y);
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int sp = 0; sp < 4; sp++)
+                w[a * 4 + sp] = G[a * 3] * v[sp] + G[a * 3 + 1] * v[4 + sp] + G[a * 3 + 2] * v[8 + sp];
+#pragma unroll
+        for (int k = 0; k < 12; k++) v[k] = w[k];
+    }
     store_spinor<SF, double>(p ? odd : even, cb, v);
 }
 
 template <int SF>
+// gm (may be NULL): psi(n) = g(n)^dag psi'(n) (back from temporal gauge)
 __global__ __launch_bounds__(BLOCK) void k_unpack_spinor(double2* __restrict__ dst, Geo g, SpinorRef even,
-                                                         SpinorRef odd, int gamma5, double scale)
+                                                         SpinorRef odd, int gamma5, double scale,
+                                                         const double2* __restrict__ gm)
 {
     const int p = blockIdx.y;
     const int cb = blockIdx.x * BLOCK + threadIdx.x;
@@ -759,10 +790,25 @@ __global__ __launch_bounds__(BLOCK) void k_unpack_spinor(double2* __restrict__ d
     using T = typename SReal<SF>::T;
     cx<T> v[12];
     load_spinor<SF, T>(p ? odd : even, cb, v);
+    cx<double> w[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) w[k] = mk<double>((double)v[k].re, (double)v[k].im);
+    if (gm) {
+        cx<double> G[9], u[12];
+#pragma unroll
+        for (int k = 0; k < 9; k++) G[k] = mk<double>(gm[n * 9 + k].x, gm[n * 9 + k].y);
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int sp = 0; sp < 4; sp++)
+                u[a * 4 + sp] = cmulc(G[a], w[sp]) + cmulc(G[3 + a], w[4 + sp]) + cmulc(G[6 + a], w[8 + sp]);
+#pragma unroll
+        for (int k = 0; k < 12; k++) w[k] = u[k];
+    }
 #pragma unroll
     for (int k = 0; k < 12; k++) {
         double sg = (gamma5 && (k & 3) >= 2) ? -scale : scale;
-        dst[n * 12 + k] = make_double2(sg * (double)v[k].re, sg * (double)v[k].im);
+        dst[n * 12 + k] = make_double2(sg * w[k].re, sg * w[k].im);
     }
 }
 
@@ -798,7 +844,7 @@ __global__ __launch_bounds__(BLOCK) void k_pack_links(const double2* __restrict_
 }
 
 // internal FP64 18-real links -> another link format (same slot layout)
-template <int LF>
+template <int SRC, int LF>
 __global__ __launch_bounds__(BLOCK) void k_convert_links(const void* __restrict__ src, void* __restrict__ dst, int Vh,
                                                          long lcs)
 {
@@ -806,8 +852,92 @@ __global__ __launch_bounds__(BLOCK) void k_convert_links(const void* __restrict_
     const int k = blockIdx.y;
     if (cb >= Vh) return;
     cx<double> W[9];
-    load_link<L64_18, double>(src, lcs, k, cb, W);
+    load_link<SRC, double>(src, lcs, k, cb, W);
     store_link<LF>(dst, lcs, k, cb, W);
+}
+
+// ---------------------------------------------------------------- temporal gauge
+// Bandwidth saving named in Sec. 4: with g(x, 0) = 1 and g(x, t + 1) = g(x, t) U_t(x, t), the
+// gauge transform U'_mu(n) = g(n) U_mu(n) g(n + mu)^dag, psi'(n) = g(n) psi(n) (M' = g M g^dag)
+// turns every time link into the unit matrix except U'_t(x, T - 1) = g(x, T - 1) U_t(x, T - 1),
+// so the hop loads and multiplies time links on the two boundary time slices only.
+// One thread per spatial site walks t; gm: canonical [V][3][3].
+__global__ __launch_bounds__(BLOCK) void k_temporal_g(const double2* __restrict__ U, Geo g, double2* __restrict__ gm)
+{
+    const long Vs = (long)g.X * g.Y * g.Z;
+    const long s = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= Vs) return;
+    const long V = Vs * g.T;
+    cx<double> G[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) G[k] = mk<double>(k % 4 == 0 ? 1.0 : 0.0, 0.0);
+    for (int t = 0; t < g.T; t++) {
+        const long n = s + Vs * t;
+#pragma unroll
+        for (int k = 0; k < 9; k++) gm[n * 9 + k] = make_double2(G[k].re, G[k].im);
+        const double2* u = U + (3 * V + n) * 9;
+        cx<double> W[9], R[9];
+#pragma unroll
+        for (int k = 0; k < 9; k++) W[k] = mk<double>(u[k].x, u[k].y);
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) R[a * 3 + b] = G[a * 3] * W[b] + G[a * 3 + 1] * W[3 + b] + G[a * 3 + 2] * W[6 + b];
+#pragma unroll
+        for (int k = 0; k < 9; k++) G[k] = R[k];
+    }
+}
+
+// U'_mu(n) = g(n) U_mu(n) g(n + mu)^dag, canonical [4][V][3][3]; time links inside the lattice are
+// written as the exact unit matrix.
+__global__ __launch_bounds__(BLOCK) void k_transform_links(const double2* __restrict__ U, const double2* __restrict__ gm,
+                                                           Geo g, double2* __restrict__ Uf)
+{
+    const long V = (long)g.X * g.Y * g.Z * g.T;
+    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (n >= V) return;
+    int c[4];
+    long r = n;
+    c[0] = (int)(r % g.X); r /= g.X;
+    c[1] = (int)(r % g.Y); r /= g.Y;
+    c[2] = (int)(r % g.Z);
+    c[3] = (int)(r / g.Z);
+    const int L[4] = {g.X, g.Y, g.Z, g.T};
+    cx<double> Gn[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) Gn[k] = mk<double>(gm[n * 9 + k].x, gm[n * 9 + k].y);
+    for (int mu = 0; mu < 4; mu++) {
+        double2* out = Uf + ((long)mu * V + n) * 9;
+        if (mu == 3 && c[3] != g.T - 1) {
+#pragma unroll
+            for (int k = 0; k < 9; k++) out[k] = make_double2(k % 4 == 0 ? 1.0 : 0.0, 0.0);
+            continue;
+        }
+        int d[4] = {c[0], c[1], c[2], c[3]};
+        d[mu] = d[mu] + 1 == L[mu] ? 0 : d[mu] + 1;
+        const long m = d[0] + (long)g.X * (d[1] + (long)g.Y * (d[2] + (long)g.Z * d[3]));
+        const double2* u = U + ((long)mu * V + n) * 9;
+        cx<double> A[9], B[9];
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++)
+                A[a * 3 + b] = Gn[a * 3] * mk<double>(u[b].x, u[b].y) + Gn[a * 3 + 1] * mk<double>(u[3 + b].x, u[3 + b].y) +
+                               Gn[a * 3 + 2] * mk<double>(u[6 + b].x, u[6 + b].y);
+        // B = A g(m)^dag: B[a][b] = sum_k A[a][k] conj(g(m)[b][k])
+        const double2* gmm = gm + m * 9;
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                cx<double> t = mk<double>(0.0, 0.0);
+#pragma unroll
+                for (int k = 0; k < 3; k++) t = t + A[a * 3 + k] * cconj(mk<double>(gmm[b * 3 + k].x, gmm[b * 3 + k].y));
+                B[a * 3 + b] = t;
+            }
+#pragma unroll
+        for (int k = 0; k < 9; k++) out[k] = make_double2(B[k].re, B[k].im);
+    }
 }
 
 // Largest deviation of row 2 from conj(row0 x row1) over all stored links (per block), which
@@ -965,14 +1095,16 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const double2* __restrict__ xs, 
 
 static inline dim3 grid1(long nblk) { return dim3((unsigned)nblk); }
 
+#define HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, STG_, TG_)                                                          \
+    hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, STG_, TG_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs, \
+                       sys, gated, exec)
 #define HOP_CASE(SF_, LF_, DAG_, RED_, FIN_)                                                                        \
     if (sf == SF_ && lf == LF_ && dag == DAG_ && red == RED_ && fin == FIN_) {                                     \
-        if (SF_ != SF64 && stage)                                                                                  \
-            hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, SF_ != SF64>), grid1(nblocks), dim3(BLOCK), 0, s, \
-                               jobs, njobs, sys, gated, exec);                                                    \
-        else                                                                                                       \
-            hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, false>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, \
-                               njobs, sys, gated, exec);                                                          \
+        const bool stg_ = SF_ != SF64 && stage;                                                                    \
+        if (stg_ && tg) HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, SF_ != SF64, !DAG_);                                \
+        else if (stg_) HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, SF_ != SF64, false);                                 \
+        else if (tg) HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, false, !DAG_);                                         \
+        else HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, false, false);                                                 \
         return hipGetLastError();                                                                                  \
     }
 #define HOP_REDS(SF_, LF_, DAG_)                                                                                   \
@@ -1000,8 +1132,9 @@ hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState
 }
 
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
-                      SysState* sys, int gated, hipStream_t s, int* exec, int stage)
+                      SysState* sys, int gated, hipStream_t s, int* exec, int stage, int tg)
 {
+    if (tg && dag) return hipErrorInvalidValue;  // the adjoint hop runs on the caller's links only
     if (nblocks <= 0) return hipSuccess;
     if (stage < 0) stage = hop_stage_default();
     HOP_REDS(SF64, L64_18, false)
@@ -1041,22 +1174,24 @@ hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long n
 }
 
 hipError_t launch_pack_spinor(int sf, const double* src, const Geo& g, SpinorRef even, SpinorRef odd, int gamma5,
-                              double scale, hipStream_t s)
+                              double scale, hipStream_t s, const double* gm)
 {
     dim3 grid((unsigned)((g.Vh + BLOCK - 1) / BLOCK), 2);
-    if (sf == SF64) hipLaunchKernelGGL((k_pack_spinor<SF64>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale);
-    else if (sf == SF32) hipLaunchKernelGGL((k_pack_spinor<SF32>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale);
-    else hipLaunchKernelGGL((k_pack_spinor<SF16>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale);
+    const double2* G = (const double2*)gm;
+    if (sf == SF64) hipLaunchKernelGGL((k_pack_spinor<SF64>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale, G);
+    else if (sf == SF32) hipLaunchKernelGGL((k_pack_spinor<SF32>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale, G);
+    else hipLaunchKernelGGL((k_pack_spinor<SF16>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale, G);
     return hipGetLastError();
 }
 
 hipError_t launch_unpack_spinor(int sf, double* dst, const Geo& g, SpinorRef even, SpinorRef odd, int gamma5,
-                                double scale, hipStream_t s)
+                                double scale, hipStream_t s, const double* gm)
 {
     dim3 grid((unsigned)((g.Vh + BLOCK - 1) / BLOCK), 2);
-    if (sf == SF64) hipLaunchKernelGGL((k_unpack_spinor<SF64>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale);
-    else if (sf == SF32) hipLaunchKernelGGL((k_unpack_spinor<SF32>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale);
-    else hipLaunchKernelGGL((k_unpack_spinor<SF16>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale);
+    const double2* G = (const double2*)gm;
+    if (sf == SF64) hipLaunchKernelGGL((k_unpack_spinor<SF64>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale, G);
+    else if (sf == SF32) hipLaunchKernelGGL((k_unpack_spinor<SF32>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale, G);
+    else hipLaunchKernelGGL((k_unpack_spinor<SF16>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale, G);
     return hipGetLastError();
 }
 
@@ -1067,16 +1202,38 @@ hipError_t launch_pack_links(const double* U, const Geo& g, void* even, void* od
     return hipGetLastError();
 }
 
-hipError_t launch_convert_links(int lf, const void* src, void* dst, int Vh, long lcs, hipStream_t s)
+#define CONVERT_CASES(SRC_)                                                                                        \
+    switch (lf) {                                                                                                  \
+    case L64_18: hipLaunchKernelGGL((k_convert_links<SRC_, L64_18>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break; \
+    case L64_12: hipLaunchKernelGGL((k_convert_links<SRC_, L64_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break; \
+    case L32_12: hipLaunchKernelGGL((k_convert_links<SRC_, L32_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break; \
+    case L16_12: hipLaunchKernelGGL((k_convert_links<SRC_, L16_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break; \
+    case LB16_12: hipLaunchKernelGGL((k_convert_links<SRC_, LB16_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break; \
+    default: return hipErrorInvalidValue;                                                                          \
+    }
+
+hipError_t launch_convert_links(int lf, int src_lf, const void* src, void* dst, int Vh, long lcs, hipStream_t s)
 {
     dim3 grid((unsigned)((Vh + BLOCK - 1) / BLOCK), 8);
-    switch (lf) {
-    case L64_12: hipLaunchKernelGGL((k_convert_links<L64_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break;
-    case L32_12: hipLaunchKernelGGL((k_convert_links<L32_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break;
-    case L16_12: hipLaunchKernelGGL((k_convert_links<L16_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break;
-    case LB16_12: hipLaunchKernelGGL((k_convert_links<LB16_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break;
-    default: return hipErrorInvalidValue;
+    if (src_lf == L64_18) {
+        CONVERT_CASES(L64_18)
+    } else if (src_lf == L64_12) {
+        CONVERT_CASES(L64_12)
+    } else {
+        return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_temporal_gauge(const double* U, const Geo& g, double* gm, double* Uf, hipStream_t s)
+{
+    const long Vs = (long)g.X * g.Y * g.Z, V = Vs * g.T;
+    hipLaunchKernelGGL(k_temporal_g, grid1((Vs + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, (const double2*)U, g,
+                       (double2*)gm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_transform_links, grid1((V + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, (const double2*)U,
+                       (const double2*)gm, g, (double2*)Uf);
     return hipGetLastError();
 }
 

@@ -10,18 +10,25 @@ enum SweepOp { OP_W = 0, OP_XR = 1, OP_S = 2, OP_SHIFT = 3, OP_INIT = 4, OP_ACC 
 
 // exec (may be NULL): incremented once per job that was not gated off. stage: LDS staging of the
 // x/y neighbours in the FP32/FP16 hop (1 on, 0 off, -1 the default of hop_stage_default()).
+// tg: some job has temporal-gauge links (HopJob::tg); must be 0 for the adjoint hop.
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
-                      SysState* sys, int gated, hipStream_t s, int* exec = nullptr, int stage = -1);
+                      SysState* sys, int gated, hipStream_t s, int* exec = nullptr, int stage = -1, int tg = 0);
 int hop_stage_default();
 hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState* sys, int gated, hipStream_t s);
 hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long nblocks, SysState* sys, int gated,
                         hipStream_t s, int* exec = nullptr);
+// gm (may be NULL): canonical [V][3][3] colour rotation g(n): pack stores g(n) psi(n), unpack
+// returns g(n)^dag psi'(n)
 hipError_t launch_pack_spinor(int sf, const double* src, const Geo& g, SpinorRef even, SpinorRef odd, int gamma5,
-                              double scale, hipStream_t s);
+                              double scale, hipStream_t s, const double* gm = nullptr);
 hipError_t launch_unpack_spinor(int sf, double* dst, const Geo& g, SpinorRef even, SpinorRef odd, int gamma5,
-                                double scale, hipStream_t s);
+                                double scale, hipStream_t s, const double* gm = nullptr);
 hipError_t launch_pack_links(const double* U, const Geo& g, void* even, void* odd, long lcs, hipStream_t s);
-hipError_t launch_convert_links(int lf, const void* src, void* dst, int Vh, long lcs, hipStream_t s);
+// internal links of format src_lf (L64_18 or L64_12) -> format lf, both output parities' halves
+// separately (called per half)
+hipError_t launch_convert_links(int lf, int src_lf, const void* src, void* dst, int Vh, long lcs, hipStream_t s);
+// temporal gauge of canonical links U: gm = g(n) [V][3][3], Uf = transformed links [4][V][3][3]
+hipError_t launch_temporal_gauge(const double* U, const Geo& g, double* gm, double* Uf, hipStream_t s);
 hipError_t launch_recon_check(const void* lk, int Vh, long lcs, double* blockmax, hipStream_t s);
 // out[2 j], out[2 j + 1] = <a, bs[j]> (j < m <= DOTS_MAX) over the real sites of full FP64 fields;
 // bs: device array of m views; partials: device, >= (2 stride / BLOCK + 1) * 2 * DOTS_MAX doubles

@@ -248,7 +248,9 @@ void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>&
         b = T.get();
         WD_CHECK_HIP(hipEventRecord(a, s));
     }
-    WD_CHECK_HIP(launch_hop(sf, lf, dag, red, fin, t.d(), t.n(), t.nblocks, sys, gated, s, flag));
+    int tg = 0;
+    for (auto& j : t.host) tg |= j.tg;
+    WD_CHECK_HIP(launch_hop(sf, lf, dag, red, fin, t.d(), t.n(), t.nblocks, sys, gated, s, flag, -1, tg));
     if (T.on) {
         WD_CHECK_HIP(hipEventRecord(b, s));
         T.pending.push_back({cls, a, b, bytes, (int)(flag - T.dflags), t.n()});
@@ -295,6 +297,14 @@ const void* wd_gauge::lk(int lf, int parity) const
     return (const char*)m->p + (size_t)parity * half;
 }
 
+const void* wd_gauge::slk(int lf, int parity) const
+{
+    if (!tg) return lk(lf, parity);
+    const DevMem* m = fixed[lf].get();
+    if (!m) throw Error{WD_ERR_ARG, "link format not prepared"};
+    return (const char*)m->p + (size_t)parity * (m->bytes / 2);
+}
+
 static size_t link_bytes(int lf, long stride)
 {
     return (size_t)2 * 8 * link_chunks(lf) * link_chunk_bytes(lf) * stride;
@@ -306,8 +316,44 @@ void wd_gauge::ensure_links(int lf, hipStream_t s)
     auto m = std::make_unique<DevMem>(link_bytes(lf, geo.stride));
     const size_t half = m->bytes / 2;
     for (int p = 0; p < 2; p++)
-        WD_CHECK_HIP(launch_convert_links(lf, lk(L64_18, p), (char*)m->p + p * half, geo.Vh, geo.stride, s));
+        WD_CHECK_HIP(launch_convert_links(lf, L64_18, lk(L64_18, p), (char*)m->p + p * half, geo.Vh, geo.stride, s));
     links[lf] = std::move(m);
+}
+
+void wd_gauge::ensure_slinks(int lf, hipStream_t s)
+{
+    if (!tg) {
+        ensure_links(lf, s);
+        return;
+    }
+    if (fixed[lf]) return;
+    // every other format is converted from the transformed 12-real FP64 links (exact for SU(3))
+    auto m = std::make_unique<DevMem>(link_bytes(lf, geo.stride));
+    const size_t half = m->bytes / 2;
+    for (int p = 0; p < 2; p++)
+        WD_CHECK_HIP(launch_convert_links(lf, L64_12, slk(L64_12, p), (char*)m->p + p * half, geo.Vh, geo.stride, s));
+    fixed[lf] = std::move(m);
+}
+
+void wd_gauge::build_temporal_gauge(const double* U, hipStream_t s)
+{
+    const size_t gbytes = (size_t)V * 9 * 16;
+    gmat = std::make_unique<DevMem>(gbytes);
+    {
+        DevMem Uf((size_t)4 * V * 9 * 16);
+        DevMem f18(link_bytes(L64_18, geo.stride));
+        WD_CHECK_HIP(hipMemsetAsync(f18.p, 0, f18.bytes, s));
+        WD_CHECK_HIP(launch_temporal_gauge(U, geo, (double*)gmat->p, (double*)Uf.p, s));
+        WD_CHECK_HIP(launch_pack_links((const double*)Uf.p, geo, f18.p, (char*)f18.p + f18.bytes / 2, geo.stride, s));
+        auto m = std::make_unique<DevMem>(link_bytes(L64_12, geo.stride));
+        const size_t half = m->bytes / 2;
+        for (int p = 0; p < 2; p++)
+            WD_CHECK_HIP(launch_convert_links(L64_12, L64_18, (const char*)f18.p + p * (f18.bytes / 2),
+                                              (char*)m->p + p * half, geo.Vh, geo.stride, s));
+        fixed[L64_12] = std::move(m);
+        WD_CHECK_HIP(hipStreamSynchronize(s));  // the temporaries are freed on return
+    }
+    tg = true;
 }
 
 Field& wd_gauge::field(const std::string& key, int sf, int halves)
@@ -339,6 +385,9 @@ size_t wd_gauge::device_bytes() const
     size_t n = 0;
     for (auto& l : links)
         if (l) n += l->bytes;
+    for (auto& l : fixed)
+        if (l) n += l->bytes;
+    if (gmat) n += gmat->bytes;
     for (auto& kv : ws) n += kv.second.mem->bytes;
     for (auto& kv : raw) n += kv.second->bytes;
     return n;

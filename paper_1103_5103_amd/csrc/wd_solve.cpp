@@ -135,7 +135,7 @@ int tune_tile(wd_gauge* g, int sf, int lf, hipStream_t st)
     std::snprintf(key, sizeof(key), "%d.%d.%d.%d.%d.%d", G.X, G.Y, G.Z, G.T, sf, lf);
     auto it = tile_cache().find(key);
     if (it != tile_cache().end()) return it->second;
-    g->ensure_links(lf, st);
+    g->ensure_slinks(lf, st);
     Field in = g->field("tune.in", sf, 1), out = g->field("tune.out", sf, 1);
     SysState* dummy = (SysState*)g->rawbuf("apply.sys", sizeof(SysState));
     hipEvent_t e0, e1;
@@ -146,16 +146,17 @@ int tune_tile(wd_gauge* g, int sf, int lf, hipStream_t st)
     for (int tz : {0, 2, 4, 8, 16}) {
         if (!tile_valid(G, tz)) continue;
         JobTable<HopJob> t;
-        HopJob j = hop_job(G, 1, 0, in.all(), out.all(), g->lk(lf, 1), g->lcs(), 1.0);
+        HopJob j = hop_job(G, 1, 0, in.all(), out.all(), g->slk(lf, 1), g->lcs(), 1.0);
+        j.tg = g->tg;
         set_tile(j, tz);
         t.host.push_back(j);
         layout(t);
         t.upload(st);
         for (int w = 0; w < 2; w++)
-            WD_CHECK_HIP(launch_hop(sf, lf, false, RED_NONE, FIN_STORE, t.d(), t.n(), t.nblocks, dummy, 0, st));
+            WD_CHECK_HIP(launch_hop(sf, lf, false, RED_NONE, FIN_STORE, t.d(), t.n(), t.nblocks, dummy, 0, st, nullptr, -1, j.tg));
         WD_CHECK_HIP(hipEventRecord(e0, st));
         for (int w = 0; w < 6; w++)
-            WD_CHECK_HIP(launch_hop(sf, lf, false, RED_NONE, FIN_STORE, t.d(), t.n(), t.nblocks, dummy, 0, st));
+            WD_CHECK_HIP(launch_hop(sf, lf, false, RED_NONE, FIN_STORE, t.d(), t.n(), t.nblocks, dummy, 0, st, nullptr, -1, j.tg));
         WD_CHECK_HIP(hipEventRecord(e1, st));
         WD_CHECK_HIP(hipEventSynchronize(e1));
         float ms = 0;
@@ -253,13 +254,15 @@ static SweepJob sweep_job(int sys, long n)
     return j;
 }
 
-// Compulsory bytes of a hop launch: every job's spinors; the links once per interleaved group.
+// Compulsory bytes of a hop launch: every job's spinors; the links once per interleaved group,
+// in temporal gauge without the unit time links (loaded on the sites of time slices 0 and T - 1)
 static double hop_bytes(const JobTable<HopJob>& t, int sf, int lf, int extra_fields)
 {
     double n = 0, nl = 0;
     for (auto& j : t.host) {
         n += (double)j.g.Vh;
-        if (j.ilv <= 1 || j.ilv_pos == 0) nl += (double)j.g.Vh;
+        const double frac = j.tg ? 0.75 + 0.25 * (j.g.T > 2 ? 2.0 / j.g.T : 1.0) : 1.0;
+        if (j.ilv <= 1 || j.ilv_pos == 0) nl += (double)j.g.Vh * frac;
     }
     return n * (2 + extra_fields) * spinor_site_bytes(sf) + nl * link_site_bytes(lf);
 }
@@ -304,7 +307,7 @@ static void prepare_source(wd_gauge* g, const std::string& key, const double* b,
 {
     src.B64 = g->field(key + "B64", SF64, 2);
     src.HB = g->field(key + "HB", SF64, 1);
-    WD_CHECK_HIP(launch_pack_spinor(SF64, b, g->geo, src.B64.half(0), src.B64.half(1), dagger, 1.0, st));
+    WD_CHECK_HIP(launch_pack_spinor(SF64, b, g->geo, src.B64.half(0), src.B64.half(1), dagger, 1.0, st, g->gm()));
     src.bb = -1;
 }
 
@@ -332,7 +335,8 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         tile_64[i] = tune_tile(S[i].g, SF64, L64, st);
     }
     for (auto& e : S) {
-        e.g->ensure_links(LFL, st);
+        e.g->ensure_slinks(LFL, st);
+        e.g->ensure_slinks(L64, st);
         const std::string k = "eo" + std::to_string(e.slot) + ".";
         if (!e.src.B64.mem) prepare_source(e.g, k, e.b, P.dagger, e.src, st);
         if (!e.X64.mem) e.X64 = e.g->field(k + "X64", SF64, 2);
@@ -376,8 +380,8 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     for (int i = 0; i < n; i++) {
         EoSys& e = S[i];
         const Geo& g = e.g->geo;
-        const void* d0 = e.g->lk(L64, 0);
-        const void* d1 = e.g->lk(L64, 1);
+        const void* d0 = e.g->slk(L64, 0);
+        const void* d1 = e.g->slk(L64, 1);
         const long lcs = e.g->lcs();
         bool shared = false;  // another system of this solve already prepares the same source
         for (int k = 0; k < i; k++) shared = shared || S[k].src.B64.base() == e.src.B64.base();
@@ -437,8 +441,8 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         sj.flags = 1;
         Acc.host.push_back(sj);
         // iteration: As = a^2 s - 1/4 D_eo D_oe s, <rhat, As>; w; Aw = M_prec w, <Aw, w>, |Aw|^2; x, r; s
-        const void* l0 = e.g->lk(LFL, 0);
-        const void* l1 = e.g->lk(LFL, 1);
+        const void* l0 = e.g->slk(LFL, 0);
+        const void* l1 = e.g->slk(LFL, 1);
         H1.host.push_back(hop_job(g, 1, i, e.s.all(), e.tmp.all(), l1, lcs, 1.0));
         j = hop_job(g, 0, i, e.tmp.all(), e.As.all(), l0, lcs, -0.25);
         j.x0 = e.s.all();
@@ -476,7 +480,10 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         for (auto& j : t->host) set_tile(j, tile_64[j.sys]);
     for (auto* t : {&H1, &H2, &H3, &H4})
         for (auto& j : t->host) set_tile(j, tile_lo[j.sys]);
-    for (auto* t : {&Hhb, &Hx1, &Hx2, &Hrec, &H1, &H2, &H3, &H4}) layout(*t);
+    for (auto* t : {&Hhb, &Hx1, &Hx2, &Hrec, &H1, &H2, &H3, &H4}) {
+        for (auto& j : t->host) j.tg = S[j.sys].g->tg;  // solver links of a temporal-gauge handle
+        layout(*t);
+    }
     for (auto* t : {&Nb, &Bp, &InitFirst, &InitRel, &InitRestart, &Acc, &Odd, &SW, &SXR, &SS}) layout(*t);
     // one copy for all tables, into a buffer kept by the first handle across solves
     upload_tables(st, S[0].g->raw["eo.tables"],
@@ -498,7 +505,8 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         any_x0 = any_x0 || e.x_ready || P.use_x0;
         if (e.x_ready) continue;
         if (P.use_x0)
-            WD_CHECK_HIP(launch_pack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st));
+            WD_CHECK_HIP(launch_pack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st,
+                                            e.g->gm()));
         else
             WD_CHECK_HIP(hipMemsetAsync(e.X64.base(), 0, e.X64.mem->bytes, st));
     }
@@ -702,7 +710,8 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         }
     }
     for (auto& e : S)
-        WD_CHECK_HIP(launch_unpack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st));
+        WD_CHECK_HIP(launch_unpack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st,
+                                          e.g->gm()));
     sys.download(st);
     for (int i = 0; i < n; i++) {
         EoSys& e = S[i];
@@ -780,7 +789,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
     q.shv = d_shv;
     sys.upload(st);
 
-    WD_CHECK_HIP(launch_pack_spinor(SF64, b, geo, B.half(0), B.half(1), P.dagger, 1.0, st));
+    WD_CHECK_HIP(launch_pack_spinor(SF64, b, geo, B.half(0), B.half(1), P.dagger, 1.0, st, g->gm()));
     const long nsites = B.nsites();
     JobTable<SweepJob> Init, SW, SXR, SEND;
     SweepJob j = sweep_job(0, nsites);
@@ -814,12 +823,14 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
     SEND.host.push_back(j);
     JobTable<HopJob> HAs, HAw;
     for (int p = 0; p < 2; p++) {
-        HopJob h = hop_job(geo, p, 0, Sv.half(1 - p), AS.half(p), g->lk(L64, p), g->lcs(), -0.5);
+        HopJob h = hop_job(geo, p, 0, Sv.half(1 - p), AS.half(p), g->slk(L64, p), g->lcs(), -0.5);
+        h.tg = g->tg;
         h.x0 = Sv.half(p);
         h.c0 = a;
         h.z = B.half(p);
         HAs.host.push_back(h);
-        h = hop_job(geo, p, 0, W.half(1 - p), AW.half(p), g->lk(L64, p), g->lcs(), -0.5);
+        h = hop_job(geo, p, 0, W.half(1 - p), AW.half(p), g->slk(L64, p), g->lcs(), -0.5);
+        h.tg = g->tg;
         h.x0 = W.half(p);
         h.c0 = a;
         HAw.host.push_back(h);
@@ -899,7 +910,8 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
         const double ai = 1.0 / (2.0 * kappas[i]);
         JobTable<HopJob> R;
         for (int p = 0; p < 2; p++) {
-            HopJob h = hop_job(geo, p, 0, Xi.half(1 - p), RES.half(p), g->lk(L64, p), g->lcs(), 0.5);
+            HopJob h = hop_job(geo, p, 0, Xi.half(1 - p), RES.half(p), g->slk(L64, p), g->lcs(), 0.5);
+            h.tg = g->tg;
             h.x0 = B.half(p);
             h.c0 = 1.0;
             h.x1 = Xi.half(p);
@@ -910,7 +922,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
         layout(R);
         R.upload(st);
         run_hop(SF64, L64, false, RED_NORM, FIN_STORE, R, sys.d(), 0, st, 0);
-        WD_CHECK_HIP(launch_unpack_spinor(SF64, x[i], geo, Xi.half(0), Xi.half(1), P.dagger, 1.0, st));
+        WD_CHECK_HIP(launch_unpack_spinor(SF64, x[i], geo, Xi.half(0), Xi.half(1), P.dagger, 1.0, st, g->gm()));
         sys.download(st);
         if (stats) {
             stats[i].iters = i == base ? iters : (sh[shift_of[i]].active ? iters : sh[shift_of[i]].conv_iter);

@@ -97,6 +97,8 @@ struct HopJob {
     // links come from memory once and from L2 for the others.
     int ilv;             // jobs in the group (1: not interleaved)
     int ilv_pos;         // position of this job in its group
+    int tg;              // links in temporal gauge: the time links are the unit matrix except
+                         // those leaving the last time slice (not loaded, not multiplied)
 };
 
 // Roles of the fields of a sweep job

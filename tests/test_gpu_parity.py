@@ -121,15 +121,19 @@ def test_bicgstab_eo_fp64(dims):
                                   # rows of X/2 sites: 36 (wider than the LDS halo), 32 (the widest
                                   # halo), 8 with 32 rows per plane (a block is one whole plane, so
                                   # the periodic y wrap stays inside the staged window)
-                                  (72, 4, 4, 4), (64, 4, 2, 4), (16, 32, 4, 4)])
-def test_bicgstab_eo_mixed(dims, spinor, links):
+                                  (72, 4, 4, 4), (64, 4, 2, 4), (16, 32, 4, 4),
+                                  # T = 2: every site sits on a boundary time slice of the
+                                  # temporal gauge (all time links are loaded)
+                                  (8, 4, 4, 2)])
+@pytest.mark.parametrize("tg", [False, True])
+def test_bicgstab_eo_mixed(dims, spinor, links, tg):
     U = li.random_links(dims, 1.0, 1005)
     b = li.gaussian_field(dims, 2005)
-    g = wd.wd_gauge_create(_t(U))
+    g = wd.wd_gauge_create(_t(U), hint=wd.params(temporal_gauge=tg))
     kappa = 0.13
     x, st = wd.bicgstab_solve(g, kappa, _t(b), p=wd.params(tol=1e-8, spinor=spinor, links=links))
     res = oracle.true_residual(U, kappa, _n(x), b)
-    _say("eo mixed", dims, spinor, links, st, "oracle residual", res)
+    _say("eo mixed", dims, spinor, links, tg, st, "oracle residual", res)
     assert st["status"] == 0
     assert res < 1e-8
     assert st["reliable_updates"] >= 1
@@ -220,6 +224,31 @@ def test_minres_guess_multimass(order):
         assert s["status"] == 0 and oracle.true_residual(U, k, _n(xg), b) < 1e-8
     assert sum(s["iters"] for s in sts) < sum(s["iters"] for s in sts0)
     g.close()
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (4, 6, 4, 10)])
+def test_temporal_gauge_solves_match_caller_gauge(dims):
+    """A handle created with temporal_gauge: its solvers work in temporal gauge (unit time links
+    except on the last time slice, sources and solutions rotated by g(n)); they give the same
+    solutions as a handle in the caller's gauge, FP64 to 1e-12 and BiCGstab-M as well."""
+    U = li.random_links(dims, 1.0, 1014)
+    b = li.gaussian_field(dims, 2014)
+    kappas = [0.124, 0.128]
+    out = {}
+    for tg in ("1", "0"):
+        g = wd.wd_gauge_create(_t(U), hint=wd.params(temporal_gauge=tg == "1"))
+        x, st = wd.bicgstab_solve(g, 0.128, _t(b), p=wd.params(tol=1e-12, mixed=False))
+        xm, stm = wd.bicgstab_m_solve(g, kappas, _t(b), p=wd.params(tol=1e-11, mixed=False, eo=False))
+        xd, std = wd.bicgstab_solve(g, 0.128, _t(b), p=wd.params(tol=1e-8, dagger=True))
+        out[tg] = (_n(x), [_n(v) for v in xm], _n(xd))
+        assert st["status"] == 0 and stm[0]["status"] == 0 and std["status"] == 0
+        g.close()
+    assert np.linalg.norm(out["1"][0] - out["0"][0]) / np.linalg.norm(out["0"][0]) < 1e-10
+    for a, c in zip(out["1"][1], out["0"][1]):
+        assert np.linalg.norm(a - c) / np.linalg.norm(c) < 1e-9
+    assert oracle.true_residual(U, 0.128, out["1"][0], b) < 1e-12
+    r = b - oracle.apply(U, 0.128, out["1"][2], dag=True)
+    assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-8
 
 
 def test_bicgstab_dagger_solves_adjoint():
