@@ -220,6 +220,9 @@ constexpr int STG_SLOTS = BLOCK_SITES + 2 * STG_H_MAX;
 template <int SF, bool ON> struct Stg {
     int unused;
 };
+template <> struct Stg<SF64, true> {
+    d2v c[12][STG_SLOTS];
+};
 template <> struct Stg<SF32, true> {
     f4v c[6][STG_SLOTS];
 };
@@ -232,7 +235,10 @@ template <> struct Stg<SF16, true> {
 template <int SF>
 __device__ __forceinline__ void stage_site(Stg<SF, true>& L, int k, const SpinorRef& r, long i)
 {
-    if constexpr (SF == SF32) {
+    if constexpr (SF == SF64) {
+#pragma unroll
+        for (int j = 0; j < 12; j++) L.c[j][k] = gld<d2v>(r.p, chunk_at(12, r.cs, i, j));
+    } else if constexpr (SF == SF32) {
 #pragma unroll
         for (int j = 0; j < 6; j++) L.c[j][k] = gld<f4v>(r.p, chunk_at(6, r.cs, i, j));
     } else {
@@ -245,7 +251,13 @@ __device__ __forceinline__ void stage_site(Stg<SF, true>& L, int k, const Spinor
 template <int SF, class T>
 __device__ __forceinline__ void load_spinor_stg(const Stg<SF, true>& L, int k, cx<T> v[12])
 {
-    if constexpr (SF == SF32) {
+    if constexpr (SF == SF64) {
+#pragma unroll
+        for (int j = 0; j < 12; j++) {
+            const d2v q = L.c[j][k];
+            v[j] = mk<T>((T)q[0], (T)q[1]);
+        }
+    } else if constexpr (SF == SF32) {
 #pragma unroll
         for (int j = 0; j < 6; j++) {
             const f4v q = L.c[j][k];

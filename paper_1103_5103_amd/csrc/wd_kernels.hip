@@ -48,6 +48,19 @@ int hop_stage_default()
     return v;
 }
 
+#ifndef WD_HOP_STAGE64
+#define WD_HOP_STAGE64 1
+#endif
+// the same for the FP64 hop (61 KB of LDS per block); environment variable WD_HOP_STAGE64
+int hop_stage64_default()
+{
+    static const int v = [] {
+        const char* e = std::getenv("WD_HOP_STAGE64");
+        return e ? (std::atoi(e) != 0) : WD_HOP_STAGE64;
+    }();
+    return v;
+}
+
 // MI355X has 8 XCDs, each with its own L2; consecutive workgroups go to consecutive XCDs. This
 // bijection on [0, nb) hands each XCD one contiguous eighth of the blocks, so the neighbour
 // sites a block gathers were mostly loaded by blocks of the same XCD and hit in its L2.
@@ -1100,9 +1113,9 @@ static inline dim3 grid1(long nblk) { return dim3((unsigned)nblk); }
                        sys, gated, exec)
 #define HOP_CASE(SF_, LF_, DAG_, RED_, FIN_)                                                                        \
     if (sf == SF_ && lf == LF_ && dag == DAG_ && red == RED_ && fin == FIN_) {                                     \
-        const bool stg_ = SF_ != SF64 && stage;                                                                    \
-        if (stg_ && tg) HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, SF_ != SF64, !DAG_);                                \
-        else if (stg_) HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, SF_ != SF64, false);                                 \
+        const bool stg_ = (SF_ != SF64 ? stage : stage64) != 0;                                                    \
+        if (stg_ && tg) HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, true, !DAG_);                                       \
+        else if (stg_) HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, true, false);                                        \
         else if (tg) HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, false, !DAG_);                                         \
         else HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, false, false);                                                 \
         return hipGetLastError();                                                                                  \
@@ -1137,6 +1150,7 @@ hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* 
     if (tg && dag) return hipErrorInvalidValue;  // the adjoint hop runs on the caller's links only
     if (nblocks <= 0) return hipSuccess;
     if (stage < 0) stage = hop_stage_default();
+    const int stage64 = hop_stage64_default();
     HOP_REDS(SF64, L64_18, false)
     HOP_CASE(SF64, L64_18, true, RED_NONE, FIN_STORE)
     HOP_REDS(SF64, L64_12, false)

@@ -14,6 +14,7 @@ enum SweepOp { OP_W = 0, OP_XR = 1, OP_S = 2, OP_SHIFT = 3, OP_INIT = 4, OP_ACC 
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
                       SysState* sys, int gated, hipStream_t s, int* exec = nullptr, int stage = -1, int tg = 0);
 int hop_stage_default();
+int hop_stage64_default();
 hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState* sys, int gated, hipStream_t s);
 hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long nblocks, SysState* sys, int gated,
                         hipStream_t s, int* exec = nullptr);
