@@ -116,6 +116,74 @@ def committed_traffic():
     return float(m.group(1)) if sha.hexdigest() == h.group(1) else None
 
 
+def other_configs(torch, dev, wd, li, np, reps):
+    """The batched and the differentiation workloads, timed beside the step.
+
+    Batched: 12 spin-colour point sources x 4 masses (kappa 0.124..0.130) on 16^3x32 plus 8^4, 12^4
+    and 16^4 lattices with 4 point sources x the same masses each (96 systems), FP16 storage, as
+    one batched solve and as 96 single-mass solves one after another. Differentiation: one forward
+    and backward pass of L = Re<eta, M(0.125)^{-1} b> on 16^3x32 in mixed precision (handle
+    creation, forward solve, adjoint solve, link gradient)."""
+    kappas = [0.124, 0.126, 0.128, 0.130]
+    lattices = [((16, 16, 16, 32), 1100, 12), ((8, 8, 8, 8), 1101, 4), ((12, 12, 12, 12), 1102, 4),
+                ((16, 16, 16, 16), 1103, 4)]
+    p = wd.params(tol=1e-8, spinor="f16", links="f16", delta=3e-3)
+    systems, gauges = [], []
+    for dims, seed, nsrc in lattices:
+        g = wd.wd_gauge_create(torch.from_numpy(li.random_links(dims, 1.0, seed)).to(dev), hint=p)
+        gauges.append(g)
+        for s in range(nsrc):
+            bd = torch.from_numpy(li.point_source(dims, spin=s % 4, colour=s // 4)).to(dev)
+            for k in kappas:
+                systems.append((g, k, bd, torch.zeros(g.field_shape, dtype=torch.complex128, device=dev)))
+    tb, ts = [], []
+    for rep in range(reps + 1):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        sts = wd.wd_batch_solve(systems, p=p)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        for g, k, bd, x in systems:
+            wd.bicgstab_solve(g, k, bd, x=x, p=p)
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        if rep > 0:
+            tb.append(b - a)
+            ts.append(c - b)
+    for g in gauges:
+        g.close()
+    batched = {"systems": len(systems), "solve_s_batched": round(float(np.median(tb)), 5),
+               "solve_s_one_by_one": round(float(np.median(ts)), 5),
+               "speedup": round(float(np.median(ts)) / float(np.median(tb)), 3),
+               "max_true_rel_res": float(f"{max(s['true_rel_res'] for s in sts):.3e}"),
+               "max_iters": max(s["iters"] for s in sts)}
+
+    dims = (16, 16, 16, 32)
+    Ud = torch.from_numpy(li.random_links(dims, 1.0, 1060)).to(dev)
+    b = torch.from_numpy(li.gaussian_field(dims, 2060)).to(dev)
+    eta = torch.from_numpy(li.gaussian_field(dims, 2061)).to(dev)
+    pg = wd.params(tol=1e-8)
+    tf, tt = [], []
+    for rep in range(reps + 1):
+        U = Ud.clone().requires_grad_(True)
+        bb = b.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        x = wd.wilson_solve(U, bb, 0.125, params=pg)
+        loss = torch.real(torch.sum(torch.conj(eta) * x))
+        torch.cuda.synchronize()
+        m = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        e = time.perf_counter()
+        if rep > 0:
+            tf.append(m - a)
+            tt.append(e - a)
+    grad = {"kappa": 0.125, "forward_s": round(float(np.median(tf)), 5),
+            "forward_backward_s": round(float(np.median(tt)), 5), "precision": "mixed (FP32 spinors, FP16 links)"}
+    return {"batched": batched, "grad": grad}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,7 +332,13 @@ def main():
                      "lo_hop_bytes_per_launch": round(seq_tg[0][2] / max(seq_tg[0][1], 1)),
                      "true_rel_res": [float(f"{s['true_rel_res']:.3e}") for s in st_tg]})
 
+    extra = other_configs(torch, dev, wd, li, np, args.steps)
     hop_gbs = hop_bytes / (hop_ms * 1e-3) / 1e9 if hop_ms > 0 else 0.0
+    vh = int(np.prod(dims)) // 2
+    sb = 96 if W["spinor"] == "f32" else 52
+    t_hop = hop_ms * 1e-3 / max(hop_n, 1)
+    effective_gbs = vh * (8 * sb + 192 + sb) / t_hop / 1e9 if t_hop > 0 else 0.0
+    gflops = vh * 1320 / t_hop / 1e9 if t_hop > 0 else 0.0
     ms_per_step = (t_end - t_start) / args.steps * 1e3
     t_mixed = float(np.median([r[0] for r in results]))
     t_ms = float(np.median([r[1] for r in results]))
@@ -301,6 +375,11 @@ def main():
         },
         "vector_add_GBps": round(peak_va, 1),
         "frac_of_vector_add": round(hop_gbs / peak_va, 4),
+        # the paper's conventions (Sec. 3): no reuse between sites (8 neighbour spinors + 8 links
+        # + 1 output spinor per site, here 8 x 96 + 192 + 96 B) and 1320 flop per site for the
+        # hopping term alone (1368 with the mass term); context for its dslash figures
+        "lo_hop_effective_GBps_paper_convention": round(effective_gbs, 1),
+        "lo_hop_GFlops": round(gflops, 1),
         "hop_launches": hop_n,
         "hop_avg_us": round(hop_ms / max(hop_n, 1) * 1e3, 2),
         "hop_bytes_per_launch": round(hop_bytes / max(hop_n, 1)),
@@ -331,6 +410,8 @@ def main():
         "true_rel_res_mixed": [float(f"{s['true_rel_res']:.3e}") for s in st_mixed],
         "true_rel_res_multishift": [float(f"{s['true_rel_res']:.3e}") for s in st_ms],
         "temporal_gauge": temporal,
+        "batched_96_systems": extra["batched"],
+        "differentiation_16x32": extra["grad"],
         "device_bytes": dev_bytes,
     }
     if not args.no_cpu:
