@@ -238,8 +238,19 @@ def multimass_sequential(U, kappas, b, tol=1e-10, maxit=10000, guess="poly", eo=
         m = float(mass_of_kappa(kappas[i]))
         k = len(done_x) if order <= 0 else min(order, len(done_x))
         if guess == "poly" and k:
-            c = poly_weights(done_m[-k:], m)
-            x0 = sum(cj * xj for cj, xj in zip(c, done_x[-k:]))
+            # distinct masses only (latest solution of a repeated mass); a repeated mass is its own guess
+            ms, xs_ = [], []
+            for mj, xj in zip(done_m[-k:], done_x[-k:]):
+                if mj in ms:
+                    i0 = ms.index(mj)
+                    del ms[i0], xs_[i0]
+                ms.append(mj)
+                xs_.append(xj)
+            if m in ms:
+                x0 = xs_[ms.index(m)].copy()
+            else:
+                c = poly_weights(ms, m)
+                x0 = sum(cj * xj for cj, xj in zip(c, xs_))
         elif guess == "minres" and k:
             x0, _ = solution_space_guess(b, done_x[-k:], done_k[-k:], kappas[i])
         x, it, st, _ = bicgstab(U, kappas[i], b, tol, maxit, x0=x0, antiperiodic=antiperiodic, eo=eo)

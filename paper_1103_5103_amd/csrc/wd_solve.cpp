@@ -1181,15 +1181,29 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
         if (guess != WD_GUESS_NONE && k > 0) {
             std::vector<double2> c(k);
             if (guess == WD_GUESS_POLY) {
-                // Lagrange weights in m a = 1/(2 kappa) - 4 (Sec. 6.2.1)
+                // Lagrange weights in m a = 1/(2 kappa) - 4 (Sec. 6.2.1) over the distinct masses
+                // among the previous ones (the latest solution of a repeated mass); a mass solved
+                // before is its own guess
                 const double m = 1.0 / (2.0 * kappas[idx]) - 4.0;
+                std::vector<bool> use(k, true);
+                int same = -1;
                 for (int jj = 0; jj < k; jj++) {
-                    const double mj = 1.0 / (2.0 * kappas[done[j_first + jj]]) - 4.0;
-                    double w = 1.0;
-                    for (int ii = 0; ii < k; ii++) {
-                        if (ii == jj) continue;
-                        const double mi = 1.0 / (2.0 * kappas[done[j_first + ii]]) - 4.0;
-                        w *= (m - mi) / (mj - mi);
+                    const double kj = kappas[done[j_first + jj]];
+                    for (int ii = jj + 1; ii < k; ii++)
+                        if (kappas[done[j_first + ii]] == kj) use[jj] = false;
+                    if (use[jj] && kj == kappas[idx]) same = jj;
+                }
+                for (int jj = 0; jj < k; jj++) {
+                    double w = 0.0;
+                    if (same >= 0) w = jj == same ? 1.0 : 0.0;
+                    else if (use[jj]) {
+                        const double mj = 1.0 / (2.0 * kappas[done[j_first + jj]]) - 4.0;
+                        w = 1.0;
+                        for (int ii = 0; ii < k; ii++) {
+                            if (ii == jj || !use[ii]) continue;
+                            const double mi = 1.0 / (2.0 * kappas[done[j_first + ii]]) - 4.0;
+                            w *= (m - mi) / (mj - mi);
+                        }
                     }
                     c[jj] = make_double2(w, 0.0);
                 }

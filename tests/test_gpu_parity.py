@@ -251,6 +251,48 @@ def test_temporal_gauge_solves_match_caller_gauge(dims):
     assert np.linalg.norm(r) / np.linalg.norm(b) < 1e-8
 
 
+@pytest.mark.parametrize("guess", ["poly", "minres"])
+def test_multimass_twelve_masses(guess):
+    """Twelve masses: the start guess combines up to eleven stored solutions (several
+    combination sweeps of 7 real or 4 complex inputs; inner products in groups of 8)."""
+    dims = (8, 8, 8, 16)
+    U = li.random_links(dims, 1.0, 1016)
+    b = li.gaussian_field(dims, 2016)
+    kappas = [0.118 + 0.0015 * k for k in range(12)]
+    g = wd.wd_gauge_create(_t(U))
+    gs = {"poly": wd.WD_GUESS_POLY, "minres": wd.WD_GUESS_MINRES}[guess]
+    xs, sts = wd.wd_multimass_solve(g, kappas, _t(b), guess=gs, p=wd.params(tol=1e-8))
+    _, sts0 = wd.wd_multimass_solve(g, kappas, _t(b), guess=wd.WD_GUESS_NONE, p=wd.params(tol=1e-8))
+    _say("twelve masses", guess, [s["iters"] for s in sts], "none", [s["iters"] for s in sts0])
+    for k, xg, s in zip(kappas, xs, sts):
+        assert s["status"] == 0 and oracle.true_residual(U, k, _n(xg), b) < 1e-8
+    assert sum(s["iters"] for s in sts) < sum(s["iters"] for s in sts0)
+    g.close()
+
+
+def test_repeated_masses_every_method():
+    """A mass listed twice: every method solves both copies; with the Lagrange guess the second
+    copy starts from the first one's solution."""
+    dims = (8, 8, 8, 8)
+    U = li.random_links(dims, 1.0, 1017)
+    b = li.gaussian_field(dims, 2017)
+    kappas = [0.124, 0.128, 0.124, 0.130, 0.130]
+    g = wd.wd_gauge_create(_t(U))
+    runs = [("poly", wd.WD_METHOD_SEQUENTIAL, wd.WD_GUESS_POLY, wd.params(tol=1e-8)),
+            ("minres", wd.WD_METHOD_SEQUENTIAL, wd.WD_GUESS_MINRES, wd.params(tol=1e-8)),
+            ("batched", wd.WD_METHOD_BATCHED, wd.WD_GUESS_NONE, wd.params(tol=1e-8)),
+            ("multishift", wd.WD_METHOD_MULTISHIFT, wd.WD_GUESS_NONE, wd.params(tol=1e-8, mixed=False, eo=False))]
+    for name, method, guess, prm in runs:
+        xs, sts = wd.wd_multimass_solve(g, kappas, _t(b), method=method, guess=guess, p=prm)
+        _say("repeated masses", name, [s["iters"] for s in sts])
+        for k, xg, s in zip(kappas, xs, sts):
+            assert s["status"] == 0 and oracle.true_residual(U, k, _n(xg), b) < 1e-8, (name, k, s)
+        if name == "poly":
+            assert sts[2]["iters"] <= 1 or sts[0]["iters"] <= 1
+            assert sts[3]["iters"] <= 1 or sts[4]["iters"] <= 1
+    g.close()
+
+
 def test_bicgstab_dagger_solves_adjoint():
     dims = (4, 4, 4, 8)
     U = li.random_links(dims, 1.0, 1006)

@@ -366,6 +366,19 @@ def test_multimass_sequential_minres_guess_and_order():
             assert sum(its) < sum(its0)
 
 
+def test_multimass_sequential_repeated_mass():
+    """A mass given twice: the Lagrange set keeps distinct masses, and the repeated mass starts
+    from its own earlier solution (already converged)."""
+    dims = (4, 4, 2, 4)
+    U = li.random_links(dims, 1.0, 1015)
+    b = li.gaussian_field(dims, 2015)
+    kappas = [0.120, 0.126, 0.120, 0.130]
+    sols, its = oracle.multimass_sequential(U, kappas, b, tol=1e-10, guess="poly")
+    for k, x in zip(kappas, sols):
+        assert oracle.true_residual(U, k, x, b) < 2e-10
+    assert min(its[0], its[2]) <= 1
+
+
 # ------------------------------------------------------------------ gradient
 
 def _loss(U, kappa, eta, b):
