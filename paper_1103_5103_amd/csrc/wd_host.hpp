@@ -133,6 +133,7 @@ struct wd_gauge {
     std::map<std::string, wd::Field> ws;              // cached workspace fields
     std::map<std::string, std::shared_ptr<wd::DevMem>> raw;
     std::map<std::string, wd::JobTable<wd::HopJob>> hop_tables;
+    std::map<std::string, std::shared_ptr<void>> graphs;  // captured iteration chunks by launch key
     hipStream_t stream = nullptr;
     double recon_err = 1.0;  // max |row2 - conj(row0 x row1)| over the links
     // FP64 operator format of the solvers: 12-real when the links are SU(3) to rounding, else 18-real

@@ -13,6 +13,7 @@
 // per-system status every `poll` iterations and performs reliable updates, restarts and
 // convergence checks.
 #include <algorithm>
+#include <type_traits>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -56,6 +57,42 @@ struct ChunkGraph {
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
+
+// A captured chunk is replayed by later solves whose launches are identical: the same kernels
+// with the same arguments (table and state buffers are kept by the handle, so their addresses
+// repeat) and grid sizes. The key lists all of them; the tables' contents (masses, fields) are
+// read by the kernels at run time.
+template <class... T>
+static std::string launch_key(const char* kind, int a, int b, int c, SysState* sys, const T&... tabs)
+{
+    std::string k = std::string(kind) + "|" + std::to_string(a) + "|" + std::to_string(b) + "|" + std::to_string(c) + "|" +
+                    std::to_string((uintptr_t)sys);
+    auto add = [&](const auto& t) {
+        int tg = 0;
+        if constexpr (std::is_same_v<std::decay_t<decltype(t)>, JobTable<HopJob>>)
+            for (auto& j : t.host) tg |= j.tg;
+        k += "|" + std::to_string((uintptr_t)t.d()) + ":" + std::to_string(t.nblocks) + ":" + std::to_string(t.n()) +
+             ":" + std::to_string(tg);
+    };
+    (add(tabs), ...);
+    return k;
+}
+
+template <class F>
+static std::shared_ptr<ChunkGraph> cached_graph(wd_gauge* g, const std::string& key, F&& body)
+{
+    auto& slot = g->graphs[key];
+    if (!slot) {
+        if (g->graphs.size() > 32) {  // bound the cache; keep the entry being made
+            g->graphs.clear();
+            return cached_graph(g, key, body);
+        }
+        auto gp = std::make_shared<ChunkGraph>();
+        gp->capture(body);
+        slot = gp;
+    }
+    return std::static_pointer_cast<ChunkGraph>(slot);
+}
 
 void set_graphs(bool on) { g_graphs = on; }
 bool graphs_on() { return g_graphs && !timer().on; }
@@ -566,11 +603,12 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         run_sweep(OP_XR, SFL, SXR, sys.d(), 1, q, bSXR);
         run_sweep(OP_S, SFL, SS, sys.d(), 1, q, bSS);
     };
-    ChunkGraph graph;
+    std::shared_ptr<ChunkGraph> graph;
     if (graphs_on())
-        graph.capture([&](hipStream_t q) {
-            for (int k = 0; k < poll; k++) iterate(q);
-        });
+        graph = cached_graph(S[0].g, launch_key("eo", poll, SFL, LFL, sys.d(), H1, H2, SW, H3, H4, SXR, SS),
+                             [&](hipStream_t q) {
+                                 for (int k = 0; k < poll; k++) iterate(q);
+                             });
     // tables restricted to a subset of the systems (the full tables when the subset is all)
     auto subset = [&](const auto& full, const std::vector<int>& ids) {
         std::remove_const_t<std::remove_reference_t<decltype(full)>> t;
@@ -612,7 +650,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     long host_iters = 0;
     const long host_cap = (long)P.max_iter + 16L * poll + 64;
     while (active > 0) {
-        if (graph.exec) graph.launch(st);
+        if (graph) graph->launch(st);
         else
             for (int k = 0; k < poll; k++) iterate(st);
         host_iters += poll;
@@ -874,9 +912,9 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
         run_sweep(OP_XR, SF64, SXR, sys.d(), 1, q, sweep_bytes(SXR, 7 * 192));
         run_sweep(endop, SF64, SEND, sys.d(), 1, q, sweep_bytes(SEND, (ns > 0 ? 6 : 4) * 192 + 4 * 192 * active_shifts));
     };
-    ChunkGraph graph;
+    std::shared_ptr<ChunkGraph> graph;
     if (graphs_on())
-        graph.capture([&](hipStream_t q) {
+        graph = cached_graph(g, launch_key("ms", poll, ns, endop, sys.d(), HAs, SW, HAw, SXR, SEND), [&](hipStream_t q) {
             for (int k = 0; k < poll; k++) iterate(ns, q);
         });
     int status = WD_OK;
@@ -886,7 +924,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
     while (true) {
         if (sys.h[0].status != ST_RUNNING) break;
         if (host_iters > host_cap) break;  // no exit state reported by the device
-        if (graph.exec) graph.launch(st);
+        if (graph) graph->launch(st);
         else
             for (int k = 0; k < poll; k++) iterate(active_shifts, st);
         host_iters += poll;
