@@ -212,8 +212,10 @@ wd_status wd_timing_get(int kernel_class, double* total_ms, long* launches, doub
 
 /*
  * Execution option: replay each chunk of solver iterations from a captured HIP graph (1) or launch
- * its kernels one by one (0, the default: capturing per solve costs more than it saves here). Results are identical either way. Graphs are not used
- * while kernel timing is enabled. Process-wide; not thread-safe against concurrent solves.
+ * its kernels one by one (0, the default). A handle keeps its captured chunks and reuses them for
+ * later solves with identical launches. Results are identical either way (measured no faster on
+ * MI355X). Graphs are not used while kernel timing is enabled. Process-wide; not thread-safe
+ * against concurrent solves.
  */
 void wd_set_graphs(int on);
 
