@@ -501,3 +501,52 @@ def test_graph_replays_match_eager_launches():
     for a, c in zip(out[True], out[False]):
         assert torch.equal(a, c)
     g.close()
+
+
+# ------------------------------------------------------------------ randomised configurations
+
+def _random_case(rng):
+    dims = tuple(int(2 * rng.integers(1, 6)) for _ in range(4))
+    return dict(dims=dims, anti=bool(rng.integers(0, 2)), kappa=float(rng.uniform(0.11, 0.13)),
+                spinor=str(rng.choice(["f32", "f16"])), links=str(rng.choice(["f16", "bf16", "f32"])),
+                tg=bool(rng.integers(0, 2)), dc=bool(rng.integers(0, 2)))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_configurations_mixed(seed):
+    """Random even extents 2..10 (rows narrower and wider than a wavefront, T = 2 included by
+    chance), either time boundary, random storage formats, temporal gauge on or off, reliable
+    updates or defect correction: every mixed solve meets 1e-8 by the oracle's operator."""
+    rng = np.random.default_rng(100 + seed)
+    c = _random_case(rng)
+    U = li.random_links(c["dims"], 1.0, 3000 + seed)
+    b = li.gaussian_field(c["dims"], 4000 + seed)
+    _say("random case", seed, c)
+    g = wd.wd_gauge_create(_t(U), antiperiodic=c["anti"], hint=wd.params(temporal_gauge=c["tg"]))
+    x, st = wd.bicgstab_solve(g, c["kappa"], _t(b), p=wd.params(tol=1e-8, spinor=c["spinor"], links=c["links"],
+                                                               delta=1e-2, defect_correction=c["dc"]))
+    res = oracle.true_residual(U, c["kappa"], _n(x), b, antiperiodic=c["anti"])
+    assert st["status"] == 0 and res < 1e-8, (c, st, res)
+    g.close()
+
+
+def test_batch_mixing_handles_of_both_gauges_and_a_non_su3_field():
+    """One FP64 batch over three handles: SU(3) links in temporal gauge, SU(3) links in the
+    caller's gauge, and non-unitary links (18-real operator). The batch then runs every handle with
+    the 18-real format, so the temporal-gauge handle uses its transformed links in that format."""
+    cases = [((4, 4, 4, 8), 1090, True, 1.0), ((6, 4, 2, 4), 1091, False, 1.0), ((4, 4, 2, 8), 1092, False, 1.05)]
+    systems, refs, gauges = [], [], []
+    for dims, seed, tg, scale in cases:
+        U = li.random_links(dims, 1.0, seed) * scale
+        g = wd.wd_gauge_create(_t(U), hint=wd.params(temporal_gauge=tg))
+        gauges.append(g)
+        b = li.gaussian_field(dims, seed + 1000)
+        for k in (0.118, 0.124):
+            systems.append((g, k, _t(b), torch.zeros(g.field_shape, dtype=torch.complex128, device=DEV)))
+            refs.append((U, k, b))
+    sts = wd.wd_batch_solve(systems, p=wd.params(tol=1e-10, mixed=False))
+    for (g, k, bd, x), (U, kk, b), s in zip(systems, refs, sts):
+        assert s["status"] == 0
+        assert oracle.true_residual(U, kk, _n(x), b) < 1e-10
+    for g in gauges:
+        g.close()
