@@ -440,6 +440,13 @@ def main():
         "iters_multishift": [s["iters"] for s in st_ms],
         "true_rel_res_mixed": [float(f"{s['true_rel_res']:.3e}") for s in st_mixed],
         "true_rel_res_multishift": [float(f"{s['true_rel_res']:.3e}") for s in st_ms],
+        "paper_context": {"hardware": "NVIDIA GTX 480 (Fermi)", "lattice": "24^4 quenched, eps 1e-10",
+                          "dslash_GFlops": {"single": 130, "double": 50}, "vector_add_GBps": 145,
+                          "dslash_effective_over_vector_add": {"paper_single": round(130 * 1.12 / 145, 2),
+                                                               "this_run": round(effective_gbs / peak_va, 2)},
+                          "single_mass_vs_multishift_speedup_narrow_set": 2.10,
+                          "note": "the paper's figures (Sec. 4, Table 3); other hardware and workload; "
+                                  "effective = the paper's no-reuse byte count"},
         "temporal_gauge": temporal,
         "batched_96_systems": extra["batched"],
         "differentiation_16x32": extra["grad"],

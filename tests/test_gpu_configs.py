@@ -87,6 +87,13 @@ def test_multimass_16x32_fp64_vs_mixed():
         assert ra < 1e-8 and rc < 1e-8, (k, ra, rc)
         # the two solutions agree within the condition number times the tolerance
         assert np.linalg.norm(_n(a) - _n(c)) / np.linalg.norm(_n(a)) < 1e-6
+    # error against the oracle's own solution, per mass (its FP64 even-odd BiCGstab to 1e-12)
+    for k, a, c in zip(kappas, xm, xs):
+        xo = oracle.bicgstab(U, k, b, tol=1e-12, eo=True)[0]
+        ea = np.linalg.norm(_n(a) - xo) / np.linalg.norm(xo)
+        ec = np.linalg.norm(_n(c) - xo) / np.linalg.norm(xo)
+        _say("16^3x32 kappa", k, "error vs oracle: BiCGstab-M", ea, "mixed sequential", ec)
+        assert ea < 1e-7 and ec < 1e-7
     g.close()
 
 
