@@ -149,8 +149,11 @@ struct wd_gauge {
 
 namespace wd {
 
-// pinned staging for small host<->device copies
+// pinned staging for small host<->device copies (one buffer: synchronise before reusing it)
 void* pinned(size_t bytes);
+// pinned ring for host-to-device copies: no synchronisation needed, since a region is only
+// handed out again after the device has drained (the ring synchronises when it wraps)
+char* stage_alloc(size_t bytes);
 
 // launch helpers with optional timing
 void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>& t, SysState* sys, int gated,

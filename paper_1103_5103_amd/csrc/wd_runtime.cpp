@@ -132,7 +132,7 @@ void Timer::flush()
 // Pinned staging for job tables: chunks are handed out in order and the arena is recycled only
 // after the device has drained (one device synchronisation per wrap-around), so uploads do not
 // wait for the stream.
-static char* stage_alloc(size_t n)
+char* stage_alloc(size_t n)
 {
     static std::mutex mu;
     static char* buf = nullptr;
