@@ -960,33 +960,49 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
     const int iters = sys.h[0].iter;
     const double t1 = now_s();
 
-    // true residual per mass and unpack
-    for (int i = 0; i < nk; i++) {
-        const Field& Xi = i == base ? X : XS[shift_of[i]];
-        const double ai = 1.0 / (2.0 * kappas[i]);
+    // true residual of every mass in one launch (one reduction group per mass; the residual
+    // fields are not kept, only their norms), then unpack
+    {
+        const size_t pstride = (size_t)NRED * (2 * geo.stride / BLOCK + 1);
+        SysArray rs;
+        rs.alloc(nk, g->raw["ms.rsys"]);
+        double* rpart = (double*)g->rawbuf("ms.rpartials", sizeof(double) * pstride * nk);
+        for (int i = 0; i < nk; i++) {
+            std::memset(&rs.h[i], 0, sizeof(SysState));
+            rs.h[i].partials = rpart + pstride * i;
+        }
         JobTable<HopJob> R;
-        for (int p = 0; p < 2; p++) {
-            HopJob h = hop_job(geo, p, 0, Xi.half(1 - p), RES.half(p), g->slk(L64, p), g->lcs(), 0.5);
-            h.tg = g->tg;
-            h.x0 = B.half(p);
-            h.c0 = 1.0;
-            h.x1 = Xi.half(p);
-            h.c1 = -ai;
-            set_tile(h, tz64);
-            R.host.push_back(h);
+        for (int i = 0; i < nk; i++) {
+            const Field& Xi = i == base ? X : XS[shift_of[i]];
+            const double ai = 1.0 / (2.0 * kappas[i]);
+            for (int p = 0; p < 2; p++) {
+                HopJob h = hop_job(geo, p, i, Xi.half(1 - p), RES.half(p), g->slk(L64, p), g->lcs(), 0.5);
+                h.tg = g->tg;
+                h.x0 = B.half(p);
+                h.c0 = 1.0;
+                h.x1 = Xi.half(p);
+                h.c1 = -ai;
+                set_tile(h, tz64);
+                R.host.push_back(h);
+            }
         }
         layout(R);
-        R.upload(st);
-        run_hop(SF64, L64, false, RED_NORM, FIN_STORE, R, sys.d(), 0, st, 0);
-        WD_CHECK_HIP(launch_unpack_spinor(SF64, x[i], geo, Xi.half(0), Xi.half(1), P.dagger, 1.0, st, g->gm()));
-        sys.download(st);
-        if (stats) {
-            stats[i].iters = i == base ? iters : (sh[shift_of[i]].active ? iters : sh[shift_of[i]].conv_iter);
-            stats[i].reliable_updates = 0;
-            stats[i].true_rel_res = bb > 0 ? std::sqrt(sys.h[0].red[2] / bb) : 0.0;
-            stats[i].status = status;
-            stats[i].seconds = t1 - t0;
+        upload_tables(st, g->raw["ms.rtables"], {&R});
+        rs.upload(st);
+        run_hop(SF64, L64, false, RED_NORM, FIN_STORE, R, rs.d(), 0, st, 0);
+        for (int i = 0; i < nk; i++) {
+            const Field& Xi = i == base ? X : XS[shift_of[i]];
+            WD_CHECK_HIP(launch_unpack_spinor(SF64, x[i], geo, Xi.half(0), Xi.half(1), P.dagger, 1.0, st, g->gm()));
         }
+        rs.download(st);
+        if (stats)
+            for (int i = 0; i < nk; i++) {
+                stats[i].iters = i == base ? iters : (sh[shift_of[i]].active ? iters : sh[shift_of[i]].conv_iter);
+                stats[i].reliable_updates = 0;
+                stats[i].true_rel_res = bb > 0 ? std::sqrt(rs.h[i].red[2] / bb) : 0.0;
+                stats[i].status = status;
+                stats[i].seconds = t1 - t0;
+            }
     }
     return (wd_status)status;
 }
