@@ -194,7 +194,7 @@ __global__ __launch_bounds__(BLOCK) void k_finish(const FinJob* __restrict__ fin
     __shared__ double lds[NRED * (BLOCK / 64)];
     const FinJob F = fin[blockIdx.x];
     SysState* S = sys + F.sys;
-    if (gated && S->status != ST_RUNNING) return;
+    if (gated && !((gated >> S->status) & 1)) return;  // gated: mask of the statuses that run
     double tot[NRED] = {0.0, 0.0, 0.0, 0.0};
     if constexpr (NR > 0) {
         for (int i = threadIdx.x; i < F.rnblk; i += BLOCK) {
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(BLOCK, HopWaves<SF>::W > 0 ? HopWaves<SF>::W : 1) v
     }
     const HopJob& J = jobs[jx];
     SysState* S = sys + J.sys;
-    if (gated && S->status != ST_RUNNING) return;
+    if (gated && !((gated >> S->status) & 1)) return;  // gated: mask of the statuses that run
     if (exec && lb == 0 && threadIdx.x == 0) atomicAdd(exec, 1);  // timing: jobs that did work
     const int cb0 = tiled_block(J, lb) * BLOCK;
     const int cb = cb0 + threadIdx.x;
@@ -474,7 +474,7 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
     const int b = blockIdx.x;
     const SweepJob& J = jobs[find_job(jobs, njobs, b)];
     SysState* S = sys + J.sys;
-    if (gated && S->status != ST_RUNNING) return;
+    if (gated && !((gated >> S->status) & 1)) return;  // gated: mask of the statuses that run
     const int lb = b - J.blk0;
     if (exec && lb == 0 && threadIdx.x == 0) atomicAdd(exec, 1);
     const long i = (long)lb * BLOCK + threadIdx.x;

@@ -581,7 +581,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         if (e.src.bb == 0.0) {  // zero source: x = 0 (also when a start vector was given)
             e.done = true;
             e.rr_true = 0;
-            sys.h[i].status = ST_CONVERGED;
+            sys.h[i].status = ST_DONE;
             WD_CHECK_HIP(hipMemsetAsync(e.X64.base(), 0, e.X64.mem->bytes, st));
             WD_CHECK_HIP(hipMemsetAsync(e.T64.base(), 0, e.T64.mem->bytes, st));
         }
@@ -591,7 +591,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         for (auto& j : InitFirst.host) j.f[R_F1] = S[j.sys].BP.all();
         InitFirst.upload(st);
     }
-    run_sweep(OP_INIT, SFL, InitFirst, sys.d(), 1, st, 0);
+    run_sweep(OP_INIT, SFL, InitFirst, sys.d(), GATE_RUN, st, 0);
     for (int i = 0; i < n; i++) S[i].t0 = t_start;
 
     const double bl = spinor_site_bytes(SFL), bx = spinor_site_bytes(SFX);
@@ -599,13 +599,13 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     const double bSW = sweep_bytes(SW, 3 * bl), bSXR = sweep_bytes(SXR, 2 * bx + 5 * bl), bSS = sweep_bytes(SS, 4 * bl);
 
     auto iterate = [&](hipStream_t q) {
-        run_hop(SFL, LFL, false, RED_NONE, FIN_STORE, H1, sys.d(), 1, q, bH1);
-        run_hop(SFL, LFL, false, RED_ZDOT, FIN_BETA, H2, sys.d(), 1, q, bH2);
-        run_sweep(OP_W, SFL, SW, sys.d(), 1, q, bSW);
-        run_hop(SFL, LFL, false, RED_NONE, FIN_STORE, H3, sys.d(), 1, q, bH1);
-        run_hop(SFL, LFL, false, RED_OUTX, FIN_CHI, H4, sys.d(), 1, q, bH4);
-        run_sweep(OP_XR, SFL, SXR, sys.d(), 1, q, bSXR);
-        run_sweep(OP_S, SFL, SS, sys.d(), 1, q, bSS);
+        run_hop(SFL, LFL, false, RED_NONE, FIN_STORE, H1, sys.d(), GATE_RUN, q, bH1);
+        run_hop(SFL, LFL, false, RED_ZDOT, FIN_BETA, H2, sys.d(), GATE_RUN, q, bH2);
+        run_sweep(OP_W, SFL, SW, sys.d(), GATE_RUN, q, bSW);
+        run_hop(SFL, LFL, false, RED_NONE, FIN_STORE, H3, sys.d(), GATE_RUN, q, bH1);
+        run_hop(SFL, LFL, false, RED_OUTX, FIN_CHI, H4, sys.d(), GATE_RUN, q, bH4);
+        run_sweep(OP_XR, SFL, SXR, sys.d(), GATE_RUN, q, bSXR);
+        run_sweep(OP_S, SFL, SS, sys.d(), GATE_RUN, q, bSS);
     };
     std::shared_ptr<ChunkGraph> graph;
     if (graphs_on())
@@ -613,40 +613,17 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
                              [&](hipStream_t q) {
                                  for (int k = 0; k < poll; k++) iterate(q);
                              });
-    // tables restricted to a subset of the systems (the full tables when the subset is all)
-    auto subset = [&](const auto& full, const std::vector<int>& ids) {
-        std::remove_const_t<std::remove_reference_t<decltype(full)>> t;
-        for (int i : ids) t.host.push_back(full.host[i]);
-        layout(t);
-        t.upload(st);
-        return t;
-    };
-    // reliable update for a subset: x_hi += x_lo, r_hi = b_prec - M_prec x_hi, |r_hi|^2
-    auto reliable_update = [&](const std::vector<int>& ids) {
+    // Reliable update of the systems that stopped (gate GATE_STOPPED; finished systems are marked
+    // ST_DONE first): x_hi += x_lo, r_hi = b_prec - M_prec x_hi, |r_hi|^2. Every step runs on the
+    // full job tables, so no per-subset tables or host synchronisation are needed.
+    auto reliable_update = [&]() {
         // the s update of the iteration in which the system stopped was gated off: apply it
         // (the scalars of that iteration are still in place), since a continuing reliable update
         // keeps s; defect correction restarts with s = r instead
-        if (!(P.mixed && P.mixed_mode == WD_MIXED_DEFECT)) {
-            if ((int)ids.size() == n) run_sweep(OP_S, SFL, SS, sys.d(), 0, st, bSS);
-            else {
-                auto T = subset(SS, ids);
-                run_sweep(OP_S, SFL, T, sys.d(), 0, st, sweep_bytes(T, 4 * bl));
-                WD_CHECK_HIP(hipStreamSynchronize(st));
-            }
-        }
-        if ((int)ids.size() == n) {
-            run_sweep(OP_ACC, SFL, Acc, sys.d(), 0, st, sweep_bytes(Acc, 2 * 192 + 2 * bx));
-            run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hx1, sys.d(), 0, st, hop_bytes(Hx1, SF64, L64, 0));
-            run_hop(SF64, L64, false, RED_NORM, FIN_STORE, Hx2, sys.d(), 0, st, hop_bytes(Hx2, SF64, L64, 2));
-            return;
-        }
-        auto A = subset(Acc, ids);
-        auto X1 = subset(Hx1, ids);
-        auto X2 = subset(Hx2, ids);
-        run_sweep(OP_ACC, SFL, A, sys.d(), 0, st, sweep_bytes(A, 2 * 192 + 2 * bx));
-        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, X1, sys.d(), 0, st, hop_bytes(X1, SF64, L64, 0));
-        run_hop(SF64, L64, false, RED_NORM, FIN_STORE, X2, sys.d(), 0, st, hop_bytes(X2, SF64, L64, 2));
-        WD_CHECK_HIP(hipStreamSynchronize(st));  // the subset tables are released on return
+        if (!(P.mixed && P.mixed_mode == WD_MIXED_DEFECT)) run_sweep(OP_S, SFL, SS, sys.d(), GATE_STOPPED, st, bSS);
+        run_sweep(OP_ACC, SFL, Acc, sys.d(), GATE_STOPPED, st, sweep_bytes(Acc, 2 * 192 + 2 * bx));
+        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hx1, sys.d(), GATE_STOPPED, st, hop_bytes(Hx1, SF64, L64, 0));
+        run_hop(SF64, L64, false, RED_NORM, FIN_STORE, Hx2, sys.d(), GATE_STOPPED, st, hop_bytes(Hx2, SF64, L64, 2));
     };
 
     int active = 0;
@@ -669,31 +646,32 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
                 }
             break;
         }
-        std::vector<int> upd;
+        bool any = false;
         for (int i = 0; i < n; i++) {
-            if (S[i].done) continue;
-            int stt = sys.h[i].status;
-            if (stt == ST_RUNNING) continue;
-            if (stt == ST_NAN) {
+            const int stt = sys.h[i].status;
+            if (S[i].done || stt == ST_RUNNING) continue;
+            if (stt == ST_NAN) {  // gated off for good: no status change needed on the device
                 S[i].done = true;
                 S[i].final_status = WD_ERR_NAN;
                 S[i].t1 = now_s();
                 active--;
                 continue;
             }
-            upd.push_back(i);
+            any = true;
         }
-        if (upd.empty()) continue;
-        reliable_update(upd);
+        if (!any) continue;
+        reliable_update();
         sys.download(st);
-        std::vector<int> cont, restart;
-        for (int i : upd) {
+        bool any_next = false, any_fresh = false;
+        for (int i = 0; i < n; i++) {
             EoSys& e = S[i];
             SysState& q = sys.h[i];
+            const int stt = q.status;
+            if (e.done || stt == ST_RUNNING || stt == ST_NAN) continue;
             e.reliable++;
             const double rr = q.red[2];
             e.rr_true = rr;
-            const int stt = q.status;
+            int next = ST_SEL1;  // continue: keep rhat and s
             if (!std::isfinite(rr)) {
                 e.done = true;
                 e.final_status = WD_ERR_NAN;
@@ -708,39 +686,26 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
                     e.done = true;
                     e.final_status = WD_ERR_BREAKDOWN;
                 } else {
-                    restart.push_back(i);
+                    next = ST_SEL2;  // restart fresh
                 }
-            } else {
-                cont.push_back(i);
             }
+            // new residual: keep rhat and s (reliable update) or restart with rhat = s = r
+            // (breakdown, and every outer step of defect correction: a fresh inner solve)
+            if (!e.done && P.mixed && P.mixed_mode == WD_MIXED_DEFECT) next = ST_SEL2;
             if (e.done) {
                 e.t1 = now_s();
                 active--;
+                q.status = ST_DONE;
+            } else {
+                q.status = next;
+                any_next = any_next || next == ST_SEL1;
+                any_fresh = any_fresh || next == ST_SEL2;
             }
         }
-        // new residual: keep rhat and s (reliable update) or restart with rhat = s = r (breakdown,
-        // and every outer step of defect correction: a fresh inner solve of M e = r)
-        if (P.mixed && P.mixed_mode == WD_MIXED_DEFECT) {
-            restart.insert(restart.end(), cont.begin(), cont.end());
-            cont.clear();
-        }
-        if (!cont.empty()) {
-            if ((int)cont.size() == n) run_sweep(OP_INIT, SFL, InitRel, sys.d(), 0, st, 0);
-            else {
-                auto I = subset(InitRel, cont);
-                run_sweep(OP_INIT, SFL, I, sys.d(), 0, st, 0);
-                WD_CHECK_HIP(hipStreamSynchronize(st));
-            }
-        }
-        if (!restart.empty()) {
-            if ((int)restart.size() == n) run_sweep(OP_INIT, SFL, InitRestart, sys.d(), 0, st, 0);
-            else {
-                std::sort(restart.begin(), restart.end());
-                auto I = subset(InitRestart, restart);
-                run_sweep(OP_INIT, SFL, I, sys.d(), 0, st, 0);
-                WD_CHECK_HIP(hipStreamSynchronize(st));
-            }
-        }
+        sys.upload(st);
+        // the restart finishers set the continuing systems RUNNING again
+        if (any_next) run_sweep(OP_INIT, SFL, InitRel, sys.d(), 1 << ST_SEL1, st, 0);
+        if (any_fresh) run_sweep(OP_INIT, SFL, InitRestart, sys.d(), 1 << ST_SEL2, st, 0);
     }
 
     // ---- finish: odd half from eq. eo3, unpack. With x_o from eq. eo3 the full residual is
@@ -749,21 +714,15 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     // Systems whose last step was an FP64 residual update reuse its D_oe x_e (T64; zero for a zero
     // source); any other system applies the hop once more.
     {
-        std::vector<int> by_sweep, by_hop;
-        for (int i = 0; i < n; i++) (S[i].reliable > 0 || S[i].src.bb == 0.0 ? by_sweep : by_hop).push_back(i);
-        if (!by_sweep.empty()) {
-            if ((int)by_sweep.size() == n) run_sweep(OP_AXPY, SF64, Odd, sys.d(), 0, st, sweep_bytes(Odd, 3 * 192));
-            else {
-                auto O = subset(Odd, by_sweep);
-                run_sweep(OP_AXPY, SF64, O, sys.d(), 0, st, sweep_bytes(O, 3 * 192));
-                WD_CHECK_HIP(hipStreamSynchronize(st));
-            }
+        int nsweep = 0;
+        for (int i = 0; i < n; i++) {
+            const bool by_sweep = S[i].reliable > 0 || S[i].src.bb == 0.0;
+            sys.h[i].status = by_sweep ? ST_SEL1 : ST_SEL2;
+            nsweep += by_sweep;
         }
-        if (!by_hop.empty()) {
-            auto R = subset(Hrec, by_hop);
-            run_hop(SF64, L64, false, RED_NONE, FIN_STORE, R, sys.d(), 0, st, hop_bytes(R, SF64, L64, 1));
-            WD_CHECK_HIP(hipStreamSynchronize(st));
-        }
+        sys.upload(st);
+        if (nsweep > 0) run_sweep(OP_AXPY, SF64, Odd, sys.d(), 1 << ST_SEL1, st, sweep_bytes(Odd, 3 * 192));
+        if (nsweep < n) run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hrec, sys.d(), 1 << ST_SEL2, st, hop_bytes(Hrec, SF64, L64, 1));
     }
     for (auto& e : S)
         WD_CHECK_HIP(launch_unpack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st,
@@ -910,11 +869,11 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
     const int endop = ns > 0 ? OP_SHIFT : OP_S;
     const double bH = hop_bytes(HAs, SF64, L64, 2);
     auto iterate = [&](int active_shifts, hipStream_t q) {
-        run_hop(SF64, L64, false, RED_ZDOT, FIN_BETA, HAs, sys.d(), 1, q, bH);
-        run_sweep(OP_W, SF64, SW, sys.d(), 1, q, sweep_bytes(SW, 3 * 192));
-        run_hop(SF64, L64, false, RED_OUTX, FIN_CHI, HAw, sys.d(), 1, q, bH - nsites * 192.0 / 2);
-        run_sweep(OP_XR, SF64, SXR, sys.d(), 1, q, sweep_bytes(SXR, 7 * 192));
-        run_sweep(endop, SF64, SEND, sys.d(), 1, q, sweep_bytes(SEND, (ns > 0 ? 6 : 4) * 192 + 4 * 192 * active_shifts));
+        run_hop(SF64, L64, false, RED_ZDOT, FIN_BETA, HAs, sys.d(), GATE_RUN, q, bH);
+        run_sweep(OP_W, SF64, SW, sys.d(), GATE_RUN, q, sweep_bytes(SW, 3 * 192));
+        run_hop(SF64, L64, false, RED_OUTX, FIN_CHI, HAw, sys.d(), GATE_RUN, q, bH - nsites * 192.0 / 2);
+        run_sweep(OP_XR, SF64, SXR, sys.d(), GATE_RUN, q, sweep_bytes(SXR, 7 * 192));
+        run_sweep(endop, SF64, SEND, sys.d(), GATE_RUN, q, sweep_bytes(SEND, (ns > 0 ? 6 : 4) * 192 + 4 * 192 * active_shifts));
     };
     std::shared_ptr<ChunkGraph> graph;
     if (graphs_on())

@@ -9,8 +9,10 @@
 // deterministic: every block of a kernel writes one partial sum, and a small follow-up kernel
 // (one block per system) adds the partials in a fixed order and then updates the scalars
 // ("finisher"). The kernel boundary orders the two, so no device-wide fence is needed inside
-// the bandwidth-bound kernels. Kernels launched with gating skip systems whose status is not
-// RUNNING, so a whole chunk of iterations can be queued without host round trips.
+// the bandwidth-bound kernels. Kernels launched with a gate (a mask of statuses) skip the
+// systems whose status is not in it: the iteration runs RUNNING systems only, so a whole chunk
+// of iterations can be queued without host round trips, and the steps between chunks (reliable
+// updates, restarts) run on the full job tables with the mask of the systems they concern.
 #pragma once
 #include "wd_device.hpp"
 
@@ -23,7 +25,13 @@ enum SysStatus {
     ST_BREAKDOWN = 3,
     ST_NAN = 4,
     ST_MAXIT = 5,
+    ST_DONE = 6,        // set by the host for a finished system of a batch (no kernel runs it)
+    ST_SEL1 = 7,        // set by the host to select systems for a gated step (e.g. continue
+    ST_SEL2 = 8,        //   after a reliable update / restart fresh; finish by sweep / by hop)
 };
+// Kernel gates are masks of the statuses allowed to run (0: no gating); GATE_RUN = the iteration.
+constexpr int GATE_RUN = 1 << ST_RUNNING;
+constexpr int GATE_STOPPED = (1 << ST_CONVERGED) | (1 << ST_RELIABLE) | (1 << ST_BREAKDOWN) | (1 << ST_MAXIT);
 
 // Finisher kinds (what the last block does with the reduced sums)
 enum Fin {
