@@ -17,6 +17,12 @@ Functions and the passages they follow:
   poly_weights              Lagrange form of the Vandermonde solve (Sec. 6.2.1)
   multimass_sequential      heaviest mass first, highest-order polynomial guess (Sec. 7)
   gauge_grad / su3_project  derivative of Re<eta, M^{-1} b> with respect to the links
+  normal_apply / cg / cg_m /
+  normal_sequential         CG and multi-shift CG-M (Sec. 8 names them as the other Krylov pair the
+                            findings carry over to) on the shifted even-site normal equations
+                            (M_prec^dag M_prec + sigma) x = b_e, the family that shares one Krylov
+                            space (Sec. 6.1); the single-shift driver mirrors Sec. 7 (largest
+                            shift first, Lagrange guess in sigma)
 """
 from __future__ import annotations
 
@@ -292,3 +298,169 @@ def dense_matrix(U, kappa, antiperiodic=True):
         e[j] = 1
         Mdense[:, j] = apply(U, kappa, e.reshape(T, Z, Y, X, 3, 4), antiperiodic=antiperiodic).ravel()
     return Mdense
+
+
+# ------------------------------------------------------------------ CG and CG-M (Sec. 8)
+
+def even_part(psi):
+    """psi with its odd sites set to zero."""
+    out = _c128(psi).copy()
+    out[parity_mask((out.shape[3], out.shape[2], out.shape[1], out.shape[0]))] = 0
+    return out
+
+
+def normal_apply(U, kappa, sigma, x_e, antiperiodic=True):
+    """(M_prec^dag M_prec + sigma) x_e on the even sites (odd sites of x_e ignored, zero on return);
+    M_prec of eq. eo4. Hermitian and positive definite for sigma >= 0."""
+    x_e = even_part(x_e)
+    y = mprec(U, kappa, x_e, antiperiodic=antiperiodic)
+    return mprec(U, kappa, y, dag=True, antiperiodic=antiperiodic) + sigma * x_e
+
+
+def _vdot(a, b):
+    return complex(np.vdot(a.ravel(), b.ravel()))
+
+
+def cg(U, kappa, sigma, b, tol=1e-10, maxit=10000, x0=None, antiperiodic=True):
+    """Conjugate gradients (Hestenes-Stiefel) on (M_prec^dag M_prec + sigma) x = b_e:
+        r = b_e - A x0, p = r
+        repeat: alpha = |r|^2 / <p, A p>;  x += alpha p;  r -= alpha A p
+                beta = |r_new|^2 / |r|^2;  p = r + beta p
+        until |r| <= tol |b_e|.
+    Returns (x, iterations, status, relative-residual history)."""
+    be = even_part(b)
+    x = np.zeros_like(be) if x0 is None else even_part(x0)
+    r = be - normal_apply(U, kappa, sigma, x, antiperiodic) if x0 is not None else be.copy()
+    p = r.copy()
+    bn = np.linalg.norm(be)
+    rr = np.vdot(r.ravel(), r.ravel()).real
+    hist = []
+    if bn == 0.0:
+        return np.zeros_like(be), 0, STATUS_OK, hist
+    it = 0
+    while np.sqrt(rr) > tol * bn:
+        if it >= maxit:
+            return x, it, STATUS_NOCONV, hist
+        Ap = normal_apply(U, kappa, sigma, p, antiperiodic)
+        pAp = _vdot(p, Ap).real
+        if pAp <= 0.0:
+            return x, it, STATUS_BREAKDOWN, hist
+        alpha = rr / pAp
+        x = x + alpha * p
+        r = r - alpha * Ap
+        rr_new = np.vdot(r.ravel(), r.ravel()).real
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        it += 1
+        hist.append(np.sqrt(rr) / bn)
+    return x, it, STATUS_OK, hist
+
+
+def cg_m(U, kappa, sigmas, b, tol=1e-10, maxit=10000, antiperiodic=True):
+    """Multi-shift CG-M on (M_prec^dag M_prec + sigma_i) x_i = b_e for all i at once, with x_i = 0
+    to start (Sec. 6.1: the shifted systems share one Krylov space). The base system is the
+    smallest shift sigma_0 (the slowest to converge); shift d_i = sigma_i - sigma_0 >= 0. The
+    residual of system i is collinear with the base residual, r^i_n = zeta^i_n r_n, and matching
+    the three-term residual recurrences of CG for A and A + d gives
+        zeta_{n+1} = zeta_n zeta_{n-1} alpha_{n-1}
+                     / (zeta_{n-1} alpha_{n-1} (1 + alpha_n d) + alpha_n beta_n (zeta_{n-1} - zeta_n))
+        alpha^i_n = alpha_n zeta_{n+1} / zeta_n,   beta^i_{n+1} = beta_{n+1} (zeta_{n+1} / zeta_n)^2
+        x^i += alpha^i_n p^i_n,   p^i_{n+1} = zeta_{n+1} r_{n+1} + beta^i_{n+1} p^i_n
+    with zeta_{-1} = zeta_0 = 1, alpha_{-1} = 1, beta_0 = 0. System i is frozen once
+    |zeta^i| |r| <= tol |b_e|; the solve stops when the base converges.
+    Returns (list of x_i in the order of sigmas, iterations, status, freeze iterations)."""
+    sig = [float(s) for s in sigmas]
+    assert min(sig) >= 0.0
+    base = int(np.argmin(sig))
+    be = even_part(b)
+    bn = np.linalg.norm(be)
+    n = len(sig)
+    xs = [np.zeros_like(be) for _ in range(n)]
+    conv = [0] * n
+    if bn == 0.0:
+        return xs, 0, STATUS_OK, conv
+    r = be.copy()
+    ps = [be.copy() for _ in range(n)]   # p^i (the base's p is ps[base])
+    z_prev = [1.0] * n
+    z = [1.0] * n
+    active = [True] * n
+    alpha_prev, beta = 1.0, 0.0
+    rr = np.vdot(r.ravel(), r.ravel()).real
+    it = 0
+    while np.sqrt(rr) > tol * bn:
+        if it >= maxit:
+            return xs, it, STATUS_NOCONV, conv
+        p = ps[base]
+        Ap = normal_apply(U, kappa, sig[base], p, antiperiodic)
+        pAp = _vdot(p, Ap).real
+        if pAp <= 0.0:
+            return xs, it, STATUS_BREAKDOWN, conv
+        alpha = rr / pAp
+        z_next = [1.0] * n
+        for i in range(n):
+            if i == base or not active[i]:
+                continue
+            d = sig[i] - sig[base]
+            z_next[i] = z[i] * z_prev[i] * alpha_prev / (
+                z_prev[i] * alpha_prev * (1.0 + alpha * d) + alpha * beta * (z_prev[i] - z[i]))
+        r = r - alpha * Ap
+        rr_new = np.vdot(r.ravel(), r.ravel()).real
+        beta_new = rr_new / rr
+        for i in range(n):
+            if not active[i]:
+                continue
+            if i == base:
+                xs[i] = xs[i] + alpha * ps[i]
+                ps[i] = r + beta_new * ps[i]
+                continue
+            a_i = alpha * z_next[i] / z[i]
+            b_i = beta_new * (z_next[i] / z[i]) ** 2
+            xs[i] = xs[i] + a_i * ps[i]
+            ps[i] = z_next[i] * r + b_i * ps[i]
+        it += 1
+        for i in range(n):
+            if i == base or not active[i]:
+                continue
+            z_prev[i], z[i] = z[i], z_next[i]
+            if abs(z[i]) * np.sqrt(rr_new) <= tol * bn:
+                active[i] = False
+                conv[i] = it
+        alpha_prev, beta, rr = alpha, beta_new, rr_new
+    conv[base] = it
+    for i in range(n):
+        if active[i]:
+            conv[i] = it
+    return xs, it, STATUS_OK, conv
+
+
+def normal_sequential(U, kappa, sigmas, b, tol=1e-10, maxit=10000, guess="poly", antiperiodic=True, order=0):
+    """CG once per shift, largest shift (best conditioned) first; with guess='poly' each start
+    vector is the Lagrange extrapolation in sigma of the solutions found so far (the analogue of
+    Sec. 6.2.1 and Sec. 7 for this family); order > 0 keeps only the most recent `order`. Returns
+    (solutions in the caller's order, iteration counts in the caller's order)."""
+    seq = sorted(range(len(sigmas)), key=lambda i: -sigmas[i])
+    sols, its = [None] * len(sigmas), [0] * len(sigmas)
+    done_s, done_x = [], []
+    for i in seq:
+        x0 = None
+        s = float(sigmas[i])
+        k = len(done_x) if order <= 0 else min(order, len(done_x))
+        if guess == "poly" and k:
+            ss, xs_ = [], []
+            for sj, xj in zip(done_s[-k:], done_x[-k:]):
+                if sj in ss:
+                    i0 = ss.index(sj)
+                    del ss[i0], xs_[i0]
+                ss.append(sj)
+                xs_.append(xj)
+            if s in ss:
+                x0 = xs_[ss.index(s)].copy()
+            else:
+                c = poly_weights(ss, s)
+                x0 = sum(cj * xj for cj, xj in zip(c, xs_))
+        x, it, st, _ = cg(U, kappa, s, b, tol, maxit, x0=x0, antiperiodic=antiperiodic)
+        sols[i], its[i] = x, it
+        done_s.append(s)
+        done_x.append(x)
+    return sols, its
+
