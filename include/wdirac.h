@@ -183,6 +183,26 @@ wd_status wd_batch_solve(int nsys, const wd_system* sys, const wd_solver_params*
                          wd_solver_stats* stats, void* stream);
 
 /*
+ * Shifted normal equations on the even sites (Sec. 8 names CG and its multi-shift form CG-M as
+ * the Krylov pair the paper's findings carry over to; shifted systems share one Krylov space,
+ * Sec. 6.1):  (M_prec^dag M_prec + sigma_i) x_i = b_e,  i < n,
+ * with M_prec = (1/(2 kappa))^2 - 1/4 D_eo D_oe the even-odd operator of eq. eo4 (Hermitian
+ * positive definite for sigma_i >= 0). b: device [V][3][4] complex128, its odd sites are ignored;
+ * x: host array of n device pointers [V][3][4], the odd sites are set to zero. method
+ * WD_METHOD_MULTISHIFT: CG-M in FP64, zero start vectors, base = the smallest shift, each other
+ * shift frozen once |zeta_i| |r| <= tol |b_e|. method WD_METHOD_SEQUENTIAL: CG once per shift,
+ * largest shift first, with WD_GUESS_POLY a start vector extrapolated (Lagrange, in sigma) from
+ * the solutions found so far (params->guess_order limits it), and params->mixed / mixed_mode /
+ * the storage formats as for bicgstab_solve (FP64 reliable updates r = b_e - (A + sigma) x, or
+ * defect correction). method WD_METHOD_BATCHED: the single-shift CG systems of all shifts
+ * iterate together, no start guesses. stats: the true residual is |b_e - (A + sigma_i) x_i| /
+ * |b_e| in FP64. 1 <= n <= 32, sigma_i >= 0, params->dagger = 0, guess NONE or POLY.
+ */
+wd_status wd_normal_solve(wd_gauge* g, double kappa, int n, const double* sigmas, double* const* x,
+                          const double* b, int method, int guess, const wd_solver_params* params,
+                          wd_solver_stats* stats, void* stream);
+
+/*
  * Link derivative of L = Re <eta, M(kappa)^{-1} b> given x = M^{-1} b and lam = M^{-dag} eta
  * (obtained by differentiating eq. 3/4 with respect to U):
  *   G_mu(n) = 1/2 s [ lam_n (1 - gamma_mu) x_{n+mu}^dag + x_n (1 + gamma_mu) lam_{n+mu}^dag ],

@@ -69,8 +69,8 @@ class System(ctypes.Structure):
 
 EXPORTED = [
     "wd_params_default", "wd_gauge_create", "wd_gauge_destroy", "wd_apply", "wd_apply_dag", "bicgstab_solve",
-    "bicgstab_m_solve", "wd_multimass_solve", "wd_batch_solve", "wd_gauge_grad", "wd_status_str",
-    "wd_last_error", "wd_timing_enable", "wd_timing_reset", "wd_timing_get", "wd_gauge_device_bytes",
+    "bicgstab_m_solve", "wd_multimass_solve", "wd_batch_solve", "wd_normal_solve", "wd_gauge_grad",
+    "wd_status_str", "wd_last_error", "wd_timing_enable", "wd_timing_reset", "wd_timing_get", "wd_gauge_device_bytes",
     "wd_set_graphs",
 ]
 
@@ -105,6 +105,8 @@ def load(path: str = LIBPATH):
                                      ctypes.POINTER(SolverParams), ctypes.POINTER(SolverStats), vp]
     L.wd_batch_solve.argtypes = [i, ctypes.POINTER(System), ctypes.POINTER(SolverParams),
                                  ctypes.POINTER(SolverStats), vp]
+    L.wd_normal_solve.argtypes = [vp, d, i, ctypes.POINTER(d), ctypes.POINTER(vp), vp, i, i,
+                                  ctypes.POINTER(SolverParams), ctypes.POINTER(SolverStats), vp]
     L.wd_gauge_grad.argtypes = [vp, vp, vp, vp, i, vp]
     L.wd_status_str.argtypes = [i]
     L.wd_status_str.restype = ctypes.c_char_p
@@ -119,8 +121,8 @@ def load(path: str = LIBPATH):
     L.wd_gauge_device_bytes.argtypes = [vp]
     L.wd_gauge_device_bytes.restype = ctypes.c_size_t
     for name in ("wd_gauge_create", "wd_gauge_destroy", "wd_apply", "wd_apply_dag", "bicgstab_solve",
-                 "bicgstab_m_solve", "wd_multimass_solve", "wd_batch_solve", "wd_gauge_grad", "wd_last_error",
-                 "wd_timing_get"):
+                 "bicgstab_m_solve", "wd_multimass_solve", "wd_batch_solve", "wd_normal_solve", "wd_gauge_grad",
+                 "wd_last_error", "wd_timing_get"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -298,6 +300,22 @@ def wd_batch_solve(systems, p: SolverParams | None = None, raise_on_fail: bool =
     code = load().wd_batch_solve(n, arr, ctypes.byref(p), st, _stream())
     _check(code, (WD_OK,) if raise_on_fail else NONFATAL)
     return [s.as_dict() for s in st]
+
+
+def wd_normal_solve(g: Gauge, kappa: float, sigmas, b: torch.Tensor, method: int = WD_METHOD_SEQUENTIAL,
+                    guess: int = WD_GUESS_POLY, xs=None, p: SolverParams | None = None,
+                    raise_on_fail: bool = True):
+    """(M_prec^dag M_prec + sigma_i) x_i = b_e on the even sites (odd sites of b ignored, of x_i
+    zero): CG per shift (sequential or batched) or CG-M (method WD_METHOD_MULTISHIFT)."""
+    p = params() if p is None else p
+    n = len(sigmas)
+    s = (ctypes.c_double * n)(*[float(v) for v in sigmas])
+    xs, arr = _xs(g, xs, n, b)
+    st = (SolverStats * n)()
+    code = load().wd_normal_solve(g.handle, float(kappa), n, s, arr, _ptr(b, "b", g.field_shape), int(method),
+                                  int(guess), ctypes.byref(p), st, _stream())
+    _check(code, (WD_OK,) if raise_on_fail else NONFATAL)
+    return xs, [q.as_dict() for q in st]
 
 
 def wd_gauge_grad(g: Gauge, x: torch.Tensor, lam: torch.Tensor, project: bool = False,

@@ -16,6 +16,8 @@ wd_status solve_multishift(wd_gauge* g, int n, const double* kappas, double* con
                            const wd_solver_params& P, wd_solver_stats* stats, hipStream_t st);
 wd_status solve_batch(int nsys, const wd_system* sys, const wd_solver_params& P, wd_solver_stats* stats,
                       hipStream_t st);
+wd_status solve_normal(wd_gauge* g, double kappa, int n, const double* sigmas, double* const* x, const double* b,
+                       int method, int guess, const wd_solver_params& P, wd_solver_stats* stats, hipStream_t st);
 wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* const* x, const double* b, int method,
                           int guess, const wd_solver_params& P, wd_solver_stats* stats, hipStream_t st);
 void set_graphs(bool on);
@@ -267,6 +269,24 @@ wd_status wd_multimass_solve(wd_gauge* g, int n, const double* kappas, double* c
         check_params(params);
         if (stats) std::memset(stats, 0, sizeof(*stats) * n);
         return solve_multimass(g, n, kappas, x, b, method, guess, *params, stats, (hipStream_t)stream);
+    });
+}
+
+wd_status wd_normal_solve(wd_gauge* g, double kappa, int n, const double* sigmas, double* const* x, const double* b,
+                          int method, int guess, const wd_solver_params* params, wd_solver_stats* stats, void* stream)
+{
+    return guarded([&]() -> wd_status {
+        if (!g || !sigmas || !x) throw Error{WD_ERR_ARG, "NULL argument"};
+        if (n < 1 || n > 32) throw Error{WD_ERR_ARG, "n must be in 1..32"};
+        if (!(kappa > 0)) throw Error{WD_ERR_ARG, "kappa must be positive"};
+        require_ptr(b, "b");
+        for (int i = 0; i < n; i++) {
+            require_ptr(x[i], "x[i]");
+            if (!(sigmas[i] >= 0) || !std::isfinite(sigmas[i])) throw Error{WD_ERR_ARG, "shifts must be finite and >= 0"};
+        }
+        check_params(params);
+        if (stats) std::memset(stats, 0, sizeof(*stats) * n);
+        return solve_normal(g, kappa, n, sigmas, x, b, method, guess, *params, stats, (hipStream_t)stream);
     });
 }
 

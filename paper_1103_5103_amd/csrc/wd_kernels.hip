@@ -169,6 +169,57 @@ __device__ void finish(SysState* S, const double* tot)
         S->maxrr = tot[2];
         S->status = (isfinite(tot[2]) && c_finite(S->delta)) ? ST_RUNNING : ST_NAN;
         S->pending = S->status;
+    } else if constexpr (FIN == FIN_CGA) {
+        // CG: alpha_n = |r_n|^2 / <p_n, A p_n> (tot[0] = Re <p, A p>; A Hermitian positive definite)
+        const double pAp = tot[0];
+        if (!isfinite(pAp)) { S->status = ST_NAN; return; }
+        if (!(pAp > 0.0)) { S->status = ST_BREAKDOWN; return; }
+        const double alpha = S->rr / pAp;
+        // CG-M: zeta_{n+1} from the collinearity of the shifted residuals, alpha^s_n = alpha_n zeta_{n+1} / zeta_n
+        for (int i = 0; i < S->nshift; i++) {
+            ShiftScal& q = S->sh[i];
+            if (!q.active) continue;
+            const double zp = q.zeta_prev.x, z = q.zeta.x;
+            const double den = zp * S->cga_prev * (1.0 + alpha * q.sigma) + alpha * S->cgb * (zp - z);
+            const double zn = z * zp * S->cga_prev / den;
+            q.zeta_next = c_real(zn);
+            q.alpha_s = c_real(alpha * zn / z);
+        }
+        S->cga = alpha;
+    } else if constexpr (FIN == FIN_CGB) {
+        // CG: beta_{n+1} = |r_{n+1}|^2 / |r_n|^2 (tot[2] = |r_{n+1}|^2) and the exit test
+        const double rr = tot[2];
+        S->iter += 1;
+        const double beta = rr / S->rr;
+        int pend = ST_RUNNING;
+        if (!isfinite(rr)) pend = ST_NAN;
+        else if (rr <= S->target2) pend = ST_CONVERGED;
+        else if (S->mixed && rr < S->delta_rel2 * S->maxrr) pend = ST_RELIABLE;
+        else if (S->iter >= S->maxit) pend = ST_MAXIT;
+        S->pending = pend;
+        // single system: commit now (the p update of a system that stops is gated off, and a
+        // continuing reliable update applies it first); CG-M commits after its shift sweep
+        if (S->nshift == 0) S->status = pend;
+        if (!S->dc && rr > S->maxrr) S->maxrr = rr;
+        for (int i = 0; i < S->nshift; i++) {
+            ShiftScal& q = S->sh[i];
+            if (!q.active) continue;
+            const double g = q.zeta_next.x / q.zeta.x;
+            q.beta_s = c_real(beta * g * g);
+            if (q.zeta_next.x * q.zeta_next.x * rr <= S->shift_target2) q.freeze = 1;
+        }
+        S->rr = rr;
+        S->cgb = beta;
+        S->cga_prev = S->cga;
+    } else if constexpr (FIN == FIN_CGEND) {
+        S->status = S->pending;
+        for (int i = 0; i < S->nshift; i++) {
+            ShiftScal& q = S->sh[i];
+            if (!q.active) continue;
+            q.zeta_prev = q.zeta;
+            q.zeta = q.zeta_next;
+            if (q.freeze) { q.active = 0; q.conv_iter = S->iter; }
+        }
     }
 }
 
@@ -665,6 +716,58 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
             }
             store_spinor<SF64, double>(J.f[R_F0], i, acc);
         }
+    } else if constexpr (OP == OP_CGX) {
+        // CG: x += alpha p ; r -= alpha A p ; |r|^2
+        if (ok) {
+            const T alpha = (T)S->cga;
+            cx<T> x[12], p[12], r[12], ap[12];
+            load_spinor<SFX, T>(J.f[R_F0], i, x);
+            load_spinor<SFL, T>(J.f[R_F1], i, p);
+#pragma unroll
+            for (int k = 0; k < 12; k++) x[k] = x[k] + alpha * p[k];
+            store_spinor<SFX, T>(J.f[R_F0], i, x);
+            load_spinor<SFL, T>(J.f[R_F2], i, r);
+            load_spinor<SFL, T>(J.f[R_F3], i, ap);
+#pragma unroll
+            for (int k = 0; k < 12; k++) r[k] = r[k] - alpha * ap[k];
+            store_spinor<SFL, T>(J.f[R_F2], i, r);
+            // the norm of the residual as stored
+            load_spinor<SFL, T>(J.f[R_F2], i, r);
+#pragma unroll
+            for (int k = 0; k < 12; k++) v[2] += (double)r[k].re * r[k].re + (double)r[k].im * r[k].im;
+        }
+        write_partials<3>(v, S, J.rblk0 + lb);
+    } else if constexpr (OP == OP_CGP || OP == OP_CGPM) {
+        // CG: p = r + beta p ; CG-M, every active shifted system:
+        //   x^s += alpha^s_n p^s ;  p^s = zeta_{n+1} r + beta^s_{n+1} p^s
+        if (ok) {
+            const T beta = (T)S->cgb;
+            cx<T> r[12], p[12];
+            load_spinor<SFL, T>(J.f[R_F1], i, r);
+            load_spinor<SFL, T>(J.f[R_F0], i, p);
+#pragma unroll
+            for (int k = 0; k < 12; k++) p[k] = r[k] + beta * p[k];
+            store_spinor<SFL, T>(J.f[R_F0], i, p);
+            if constexpr (OP == OP_CGPM) {
+                const int ns = S->nshift;
+                for (int q = 0; q < ns; q++) {
+                    const ShiftScal& Q = S->sh[q];
+                    if (!Q.active) continue;
+                    const SpinorRef xr = S->shv[2 * q], pr = S->shv[2 * q + 1];
+                    const T as = (T)Q.alpha_s.x, bs = (T)Q.beta_s.x, zn = (T)Q.zeta_next.x;
+                    cx<T> xs[12], ps[12];
+                    load_spinor<SFL, T>(xr, i, xs);
+                    load_spinor<SFL, T>(pr, i, ps);
+#pragma unroll
+                    for (int k = 0; k < 12; k++) {
+                        xs[k] = xs[k] + as * ps[k];
+                        ps[k] = zn * r[k] + bs * ps[k];
+                    }
+                    store_spinor<SFL, T>(xr, i, xs);
+                    store_spinor<SFL, T>(pr, i, ps);
+                }
+            }
+        }
     } else if constexpr (OP == OP_MSINIT) {
         // BiCGstab-M start: r = s = rhat = b, x = 0, x^sigma = 0, s^sigma = b; |b|^2
         if (ok) {
@@ -1111,8 +1214,10 @@ static inline dim3 grid1(long nblk) { return dim3((unsigned)nblk); }
 #define HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, STG_, TG_)                                                          \
     hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, STG_, TG_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs, \
                        sys, gated, exec)
+// The kernel does not depend on the finisher run after it (FIN_ names the instantiation only): the
+// launch is chosen by the reduction kind.
 #define HOP_CASE(SF_, LF_, DAG_, RED_, FIN_)                                                                        \
-    if (sf == SF_ && lf == LF_ && dag == DAG_ && red == RED_ && fin == FIN_) {                                     \
+    if (sf == SF_ && lf == LF_ && dag == DAG_ && red == RED_) {                                                    \
         const bool stg_ = (SF_ != SF64 ? stage : stage64) != 0;                                                    \
         if (stg_ && tg) HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, true, !DAG_);                                       \
         else if (stg_) HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, true, false);                                        \
@@ -1125,6 +1230,11 @@ static inline dim3 grid1(long nblk) { return dim3((unsigned)nblk); }
     HOP_CASE(SF_, LF_, DAG_, RED_NORM, FIN_STORE)                                                                  \
     HOP_CASE(SF_, LF_, DAG_, RED_ZDOT, FIN_BETA)                                                                   \
     HOP_CASE(SF_, LF_, DAG_, RED_OUTX, FIN_CHI)
+// the adjoint hops of the normal equations (CG): the iteration's two, plus the FP64 residual's
+#define HOP_DAG_LO(SF_, LF_)                                                                                       \
+    HOP_CASE(SF_, LF_, true, RED_NONE, FIN_STORE)                                                                  \
+    HOP_CASE(SF_, LF_, true, RED_ZDOT, FIN_BETA)
+#define HOP_DAG_64(LF_) HOP_DAG_LO(SF64, LF_) HOP_CASE(SF64, LF_, true, RED_NORM, FIN_STORE)
 
 #define FIN_CASE(NR_, FIN_)                                                                                        \
     if (nr == NR_ && fin == FIN_) {                                                                                \
@@ -1141,6 +1251,9 @@ hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState
     FIN_CASE(3, FIN_ALPHA)
     FIN_CASE(3, FIN_RESTART)
     FIN_CASE(0, FIN_END)
+    FIN_CASE(3, FIN_CGA)
+    FIN_CASE(3, FIN_CGB)
+    FIN_CASE(0, FIN_CGEND)
     return hipErrorInvalidValue;
 }
 
@@ -1152,7 +1265,6 @@ hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* 
     if (stage < 0) stage = hop_stage_default();
     const int stage64 = hop_stage64_default();
     HOP_REDS(SF64, L64_18, false)
-    HOP_CASE(SF64, L64_18, true, RED_NONE, FIN_STORE)
     HOP_REDS(SF64, L64_12, false)
     HOP_REDS(SF32, L32_12, false)
     HOP_REDS(SF32, L16_12, false)
@@ -1160,6 +1272,14 @@ hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* 
     HOP_REDS(SF16, L32_12, false)
     HOP_REDS(SF16, L16_12, false)
     HOP_REDS(SF16, LB16_12, false)
+    HOP_DAG_64(L64_18)
+    HOP_DAG_64(L64_12)
+    HOP_DAG_LO(SF32, L32_12)
+    HOP_DAG_LO(SF32, L16_12)
+    HOP_DAG_LO(SF32, LB16_12)
+    HOP_DAG_LO(SF16, L32_12)
+    HOP_DAG_LO(SF16, L16_12)
+    HOP_DAG_LO(SF16, LB16_12)
     return hipErrorInvalidValue;
 }
 
@@ -1170,7 +1290,8 @@ hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* 
     }
 #define SWEEP_ALL(SF_)                                                                                             \
     SWEEP_CASE(OP_W, SF_)                                                                                          \
-    SWEEP_CASE(OP_XR, SF_) SWEEP_CASE(OP_S, SF_) SWEEP_CASE(OP_INIT, SF_) SWEEP_CASE(OP_ACC, SF_)
+    SWEEP_CASE(OP_XR, SF_) SWEEP_CASE(OP_S, SF_) SWEEP_CASE(OP_INIT, SF_) SWEEP_CASE(OP_ACC, SF_)                 \
+    SWEEP_CASE(OP_CGX, SF_) SWEEP_CASE(OP_CGP, SF_)
 
 hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long nblocks, SysState* sys, int gated,
                         hipStream_t s, int* exec)
@@ -1184,6 +1305,7 @@ hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long n
     SWEEP_CASE(OP_MSINIT, SF64)
     SWEEP_CASE(OP_AXPY, SF64)
     SWEEP_CASE(OP_LINCOMB, SF64)
+    SWEEP_CASE(OP_CGPM, SF64)
     return hipErrorInvalidValue;
 }
 

@@ -6,7 +6,7 @@ namespace wd {
 
 enum HopRed { RED_NONE = 0, RED_ZDOT = 1, RED_OUTX = 2, RED_NORM = 3 };
 enum SweepOp { OP_W = 0, OP_XR = 1, OP_S = 2, OP_SHIFT = 3, OP_INIT = 4, OP_ACC = 5, OP_NORM = 6, OP_MSINIT = 7, OP_AXPY = 8,
-               OP_LINCOMB = 9 };
+               OP_LINCOMB = 9, OP_CGX = 10, OP_CGP = 11, OP_CGPM = 12 };
 
 // exec (may be NULL): incremented once per job that was not gated off. stage: LDS staging of the
 // x/y neighbours in the FP32/FP16 hop (1 on, 0 off, -1 the default of hop_stage_default()).

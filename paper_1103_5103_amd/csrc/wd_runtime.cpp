@@ -280,6 +280,8 @@ void run_sweep(int op, int sfl, const JobTable<SweepJob>& t, SysState* sys, int 
     case OP_INIT:
     case OP_MSINIT: run_finish(3, FIN_RESTART, t, sys, gated, s); break;
     case OP_NORM: run_finish(3, FIN_STORE, t, sys, gated, s); break;
+    case OP_CGX: run_finish(3, FIN_CGB, t, sys, gated, s); break;
+    case OP_CGPM: run_finish(0, FIN_CGEND, t, sys, gated, s); break;  // OP_CGP: committed in FIN_CGB
     default: break;
     }
 }

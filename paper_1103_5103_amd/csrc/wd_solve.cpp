@@ -1284,4 +1284,708 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
     return worst;
 }
 
+
+// ================================================================ CG / CG-M on the shifted normal equations
+
+// The even-site systems (M_prec^dag M_prec + sigma) x = b_e, M_prec of eq. eo4 (Sec. 8 names CG and
+// CG-M as the Krylov pair the findings carry over to; the shifted family shares one Krylov space,
+// Sec. 6.1). A = M_prec^dag M_prec is applied as four hops: t = D_oe p, v = a^2 p - 1/4 D_eo t,
+// t = (D_eo)^dag v, A p + sigma p = a^2 v - 1/4 (D_oe)^dag t + sigma p, the adjoint hops being the
+// parity blocks of D^dag = gamma5 D gamma5 on the same links.
+struct CgSys {
+    wd_gauge* g;
+    double kappa, a, sigma;
+    const double* b;
+    double* x;
+    int slot;
+    EoSource src;          // packed b (shared by systems with the same source)
+    double be2 = -1;       // |b_e|^2 (computed here when negative)
+    Field X64;             // FP64 solution: even half iterated, odd half zero
+    bool x_ready = false;  // the even half of X64 holds the start vector, the odd half is zero
+    Field RH, T64, V64;    // FP64 residual (even) and operator temporaries (odd, even)
+    Field r, p, t, v, w, xl;
+    bool done = false;
+    int restarts = 0, reliable = 0, final_status = WD_OK, iters = 0;
+    double rr_true = -1, true_rel = 0, t0 = 0, t1 = 0;
+};
+
+// Single-shift CG for a batch of systems (one launch per solver step for all of them), in the
+// precision scheme of the even-odd BiCGstab: low-precision iteration, FP64 reliable updates
+// (x_hi += x_lo, r_hi = b_e - (A + sigma) x_hi in FP64) or defect correction, an FP64 check of
+// every exit.
+static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream_t st, int poll)
+{
+    const int n = (int)S.size();
+    const int SFL = P.mixed ? spinor_fmt_of(P.spinor_store) : SF64;
+    const int SFX = SFL == SF64 ? SF64 : SF32;
+    int L64 = L64_12;
+    for (auto& e : S)
+        if (e.g->f64_links() != L64_12) L64 = L64_18;
+    const int LFL = P.mixed ? link_fmt_of(P.link_store, P.recon) : L64;
+    if (P.mixed && link_recon12(LFL))
+        for (auto& e : S)
+            if (e.g->recon_err > 1e-6)
+                throw Error{WD_ERR_UNSUPPORTED, "links are not SU(3): the 12-real low-precision formats would change "
+                                                "the operator; solve with mixed = 0"};
+    const double t_start = now_s();
+    std::vector<int> tile_lo(n), tile_64(n);
+    for (int i = 0; i < n; i++) {
+        tile_lo[i] = tune_tile(S[i].g, SFL, LFL, st);
+        tile_64[i] = tune_tile(S[i].g, SF64, L64, st);
+    }
+    for (auto& e : S) {
+        e.g->ensure_slinks(LFL, st);
+        e.g->ensure_slinks(L64, st);
+        const std::string k = "cg" + std::to_string(e.slot) + ".";
+        if (!e.src.B64.mem) prepare_source(e.g, k, e.b, 0, e.src, st);
+        if (!e.X64.mem) e.X64 = e.g->field(k + "X64", SF64, 2);
+        e.RH = e.g->field(k + "RH", SF64, 1);
+        e.T64 = e.g->field(k + "T64", SF64, 1);
+        e.V64 = e.g->field(k + "V64", SF64, 1);
+        e.r = e.g->field(k + "r", SFL, 1);
+        e.p = e.g->field(k + "p", SFL, 1);
+        e.t = e.g->field(k + "t", SFL, 1);
+        e.v = e.g->field(k + "v", SFL, 1);
+        e.w = e.g->field(k + "w", SFL, 1);
+        e.xl = e.g->field(k + "xl", SFX, 1);
+        e.a = 1.0 / (2.0 * e.kappa);
+    }
+
+    SysArray sys;
+    sys.alloc(n, S[0].g->raw["cg.sys"]);
+    for (int i = 0; i < n; i++) {
+        CgSys& e = S[i];
+        SysState& q = sys.h[i];
+        std::memset(&q, 0, sizeof(q));
+        q.partials = (double*)e.g->rawbuf("cg" + std::to_string(e.slot) + ".partials",
+                                          sizeof(double) * NRED * (2 * e.g->geo.stride / BLOCK + 1));
+        q.maxit = P.max_iter;
+        q.mixed = P.mixed;
+        q.delta_rel2 = P.delta_reliable * P.delta_reliable;
+        q.dc = P.mixed && P.mixed_mode == WD_MIXED_DEFECT;
+        q.target2 = -1.0;
+        q.cga_prev = 1.0;
+        q.status = ST_RUNNING;
+    }
+    sys.upload(st);
+
+    JobTable<SweepJob> Nb, Bs, Acc, InitFirst, InitRel, InitRestart, SX, SP;
+    JobTable<HopJob> Hx1, Hx2, Hx3, Hx4, H1, H2, H3, H4;
+    std::vector<int> need_norm;
+    for (int i = 0; i < n; i++) {
+        CgSys& e = S[i];
+        const Geo& g = e.g->geo;
+        const void* d0 = e.g->slk(L64, 0);
+        const void* d1 = e.g->slk(L64, 1);
+        const void* l0 = e.g->slk(LFL, 0);
+        const void* l1 = e.g->slk(LFL, 1);
+        const long lcs = e.g->lcs();
+        const double a2 = e.a * e.a;
+        bool shared = false;
+        for (int k = 0; k < i; k++) shared = shared || S[k].src.B64.base() == e.src.B64.base();
+        if (e.be2 < 0 && !shared) {
+            need_norm.push_back(i);
+            SweepJob nj = sweep_job(i, e.RH.nsites());
+            nj.f[R_F0] = e.src.B64.half(0);
+            Nb.host.push_back(nj);
+        }
+        // RH = b_e - sigma x_e
+        SweepJob sj = sweep_job(i, e.RH.nsites());
+        sj.f[R_F0] = e.RH.all();
+        sj.f[R_F1] = e.src.B64.half(0);
+        sj.f[R_F2] = e.X64.half(0);
+        sj.c[0] = 1.0;
+        sj.c[1] = -e.sigma;
+        Bs.host.push_back(sj);
+        sj = sweep_job(i, e.xl.nsites());
+        sj.f[R_F0] = e.X64.half(0);
+        sj.f[R_F1] = e.xl.all();
+        sj.flags = 1;
+        Acc.host.push_back(sj);
+        // FP64 residual: T64 = D_oe x ; V64 = M_prec x ; T64 = (D_eo)^dag V64 ;
+        // RH <- RH - a^2 V64 + 1/4 (D_oe)^dag T64 = b_e - (A + sigma) x, |RH|^2
+        Hx1.host.push_back(hop_job(g, 1, i, e.X64.half(0), e.T64.all(), d1, lcs, 1.0));
+        HopJob j = hop_job(g, 0, i, e.T64.all(), e.V64.all(), d0, lcs, -0.25);
+        j.x0 = e.X64.half(0);
+        j.c0 = a2;
+        Hx2.host.push_back(j);
+        Hx3.host.push_back(hop_job(g, 1, i, e.V64.all(), e.T64.all(), d1, lcs, 1.0));
+        j = hop_job(g, 0, i, e.T64.all(), e.RH.all(), d0, lcs, 0.25);
+        j.x0 = e.RH.all();
+        j.c0 = 1.0;
+        j.x1 = e.V64.all();
+        j.c1 = -a2;
+        Hx4.host.push_back(j);
+        // r_lo = r_hi (FP64 residual or, without a start vector, b_e); p = r; x_lo = 0; |r|^2
+        sj = sweep_job(i, e.r.nsites());
+        sj.f[R_F0] = e.r.all();
+        sj.f[R_F1] = e.RH.all();
+        sj.f[R_F2] = e.r.all();
+        sj.f[R_F3] = e.p.all();
+        sj.f[R_F4] = e.xl.all();
+        sj.flags = 2 | 4;
+        InitFirst.host.push_back(sj);
+        sj.flags = 0;
+        InitRel.host.push_back(sj);
+        sj.flags = 2;
+        InitRestart.host.push_back(sj);
+        // iteration: t = D_oe p ; v = M_prec p ; t = (D_eo)^dag v ; w = (A + sigma) p, <p, w> ;
+        // x += alpha p, r -= alpha w, |r|^2 ; p = r + beta p
+        H1.host.push_back(hop_job(g, 1, i, e.p.all(), e.t.all(), l1, lcs, 1.0));
+        j = hop_job(g, 0, i, e.t.all(), e.v.all(), l0, lcs, -0.25);
+        j.x0 = e.p.all();
+        j.c0 = a2;
+        H2.host.push_back(j);
+        H3.host.push_back(hop_job(g, 1, i, e.v.all(), e.t.all(), l1, lcs, 1.0));
+        j = hop_job(g, 0, i, e.t.all(), e.w.all(), l0, lcs, -0.25);
+        j.x0 = e.v.all();
+        j.c0 = a2;
+        j.x1 = e.p.all();
+        j.c1 = e.sigma;
+        j.z = e.p.all();
+        H4.host.push_back(j);
+        sj = sweep_job(i, e.r.nsites());
+        sj.f[R_F0] = e.xl.all();
+        sj.f[R_F1] = e.p.all();
+        sj.f[R_F2] = e.r.all();
+        sj.f[R_F3] = e.w.all();
+        SX.host.push_back(sj);
+        sj = sweep_job(i, e.r.nsites());
+        sj.f[R_F0] = e.p.all();
+        sj.f[R_F1] = e.r.all();
+        SP.host.push_back(sj);
+    }
+    for (auto* t : {&Hx1, &Hx2, &Hx3, &Hx4})
+        for (auto& j : t->host) set_tile(j, tile_64[j.sys]);
+    for (auto* t : {&H1, &H2, &H3, &H4})
+        for (auto& j : t->host) set_tile(j, tile_lo[j.sys]);
+    // the forward hops skip the unit time links of a temporal-gauge handle; the adjoint hops read
+    // every link (all of them are stored)
+    for (auto* t : {&Hx1, &Hx2, &H1, &H2})
+        for (auto& j : t->host) j.tg = S[j.sys].g->tg;
+    for (auto* t : {&Hx1, &Hx2, &Hx3, &Hx4, &H1, &H2, &H3, &H4}) layout(*t);
+    for (auto* t : {&Nb, &Bs, &Acc, &InitFirst, &InitRel, &InitRestart, &SX, &SP}) layout(*t);
+    upload_tables(st, S[0].g->raw["cg.tables"],
+                  {&Hx1, &Hx2, &Hx3, &Hx4, &H1, &H2, &H3, &H4, &Nb, &Bs, &Acc, &InitFirst, &InitRel, &InitRestart,
+                   &SX, &SP});
+
+    const double bl = spinor_site_bytes(SFL), bx = spinor_site_bytes(SFX);
+    const double bHx1 = hop_bytes(Hx1, SF64, L64, 0), bHx2 = hop_bytes(Hx2, SF64, L64, 1),
+                 bHx4 = hop_bytes(Hx4, SF64, L64, 2);
+    auto residual = [&](int gate) {
+        run_sweep(OP_AXPY, SF64, Bs, sys.d(), gate, st, sweep_bytes(Bs, 3 * 192));
+        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hx1, sys.d(), gate, st, bHx1);
+        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hx2, sys.d(), gate, st, bHx2);
+        run_hop(SF64, L64, true, RED_NONE, FIN_STORE, Hx3, sys.d(), gate, st, bHx1);
+        run_hop(SF64, L64, true, RED_NORM, FIN_STORE, Hx4, sys.d(), gate, st, bHx4);
+    };
+
+    // ---- setup: |b_e|^2 (one round trip, skipped when the caller knows it), start residual
+    if (!need_norm.empty()) {
+        run_sweep(OP_NORM, SF64, Nb, sys.d(), 0, st, sweep_bytes(Nb, 192));
+        sys.download(st);
+        for (int i : need_norm) S[i].be2 = sys.h[i].red[2];
+        for (int i = 0; i < n; i++)
+            for (int k : need_norm)
+                if (S[i].be2 < 0 && S[i].src.B64.base() == S[k].src.B64.base()) S[i].be2 = S[k].be2;
+    }
+    bool any_x0 = false;
+    for (auto& e : S) {
+        // the odd half stays zero: the solution lives on the even sites
+        if (!e.x_ready) WD_CHECK_HIP(hipMemsetAsync(e.X64.base(), 0, e.X64.mem->bytes, st));
+        any_x0 = any_x0 || e.x_ready;
+    }
+    if (any_x0) residual(0);
+    for (int i = 0; i < n; i++) {
+        CgSys& e = S[i];
+        sys.h[i].target2 = P.tol * P.tol * e.be2;
+        sys.h[i].status = ST_RUNNING;
+        if (e.be2 == 0.0) {  // zero source: x = 0
+            e.done = true;
+            e.rr_true = 0;
+            sys.h[i].status = ST_DONE;
+            WD_CHECK_HIP(hipMemsetAsync(e.X64.base(), 0, e.X64.mem->bytes, st));
+        }
+    }
+    sys.upload(st);
+    if (!any_x0) {
+        for (auto& j : InitFirst.host) j.f[R_F1] = S[j.sys].src.B64.half(0);
+        InitFirst.upload(st);
+    }
+    run_sweep(OP_INIT, SFL, InitFirst, sys.d(), GATE_RUN, st, 0);
+    for (int i = 0; i < n; i++) S[i].t0 = t_start;
+
+    const double bH = hop_bytes(H1, SFL, LFL, 0), bH2 = hop_bytes(H2, SFL, LFL, 1), bH4 = hop_bytes(H4, SFL, LFL, 2);
+    const double bSX = sweep_bytes(SX, 2 * bx + 4 * bl), bSP = sweep_bytes(SP, 3 * bl);
+    auto iterate = [&](hipStream_t q) {
+        run_hop(SFL, LFL, false, RED_NONE, FIN_STORE, H1, sys.d(), GATE_RUN, q, bH);
+        run_hop(SFL, LFL, false, RED_NONE, FIN_STORE, H2, sys.d(), GATE_RUN, q, bH2);
+        run_hop(SFL, LFL, true, RED_NONE, FIN_STORE, H3, sys.d(), GATE_RUN, q, bH);
+        run_hop(SFL, LFL, true, RED_ZDOT, FIN_CGA, H4, sys.d(), GATE_RUN, q, bH4);
+        run_sweep(OP_CGX, SFL, SX, sys.d(), GATE_RUN, q, bSX);
+        run_sweep(OP_CGP, SFL, SP, sys.d(), GATE_RUN, q, bSP);
+    };
+    std::shared_ptr<ChunkGraph> graph;
+    if (graphs_on())
+        graph = cached_graph(S[0].g, launch_key("cg", poll, SFL, LFL, sys.d(), H1, H2, H3, H4, SX, SP),
+                             [&](hipStream_t q) {
+                                 for (int k = 0; k < poll; k++) iterate(q);
+                             });
+    // Reliable update of the systems that stopped (gate GATE_STOPPED): the p update of the
+    // iteration in which a system stopped was gated off; a continuing reliable update keeps p, so
+    // apply it first (defect correction restarts with p = r instead)
+    auto reliable_update = [&]() {
+        if (!(P.mixed && P.mixed_mode == WD_MIXED_DEFECT)) run_sweep(OP_CGP, SFL, SP, sys.d(), GATE_STOPPED, st, bSP);
+        run_sweep(OP_ACC, SFL, Acc, sys.d(), GATE_STOPPED, st, sweep_bytes(Acc, 2 * 192 + 2 * bx));
+        residual(GATE_STOPPED);
+    };
+
+    int active = 0;
+    for (auto& e : S) active += !e.done;
+    long host_iters = 0;
+    const long host_cap = (long)P.max_iter + 16L * poll + 64;
+    while (active > 0) {
+        if (graph) graph->launch(st);
+        else
+            for (int k = 0; k < poll; k++) iterate(st);
+        host_iters += poll;
+        sys.download(st);
+        if (host_iters > host_cap) {
+            for (auto& e : S)
+                if (!e.done) {
+                    e.done = true;
+                    e.final_status = WD_ERR_NOCONV;
+                    e.t1 = now_s();
+                }
+            break;
+        }
+        bool any = false;
+        for (int i = 0; i < n; i++) {
+            const int stt = sys.h[i].status;
+            if (S[i].done || stt == ST_RUNNING) continue;
+            if (stt == ST_NAN) {
+                S[i].done = true;
+                S[i].final_status = WD_ERR_NAN;
+                S[i].t1 = now_s();
+                active--;
+                continue;
+            }
+            any = true;
+        }
+        if (!any) continue;
+        reliable_update();
+        sys.download(st);
+        bool any_next = false, any_fresh = false;
+        for (int i = 0; i < n; i++) {
+            CgSys& e = S[i];
+            SysState& q = sys.h[i];
+            const int stt = q.status;
+            if (e.done || stt == ST_RUNNING || stt == ST_NAN) continue;
+            e.reliable++;
+            const double rr = q.red[2];
+            e.rr_true = rr;
+            int next = ST_SEL1;  // continue: keep p
+            if (!std::isfinite(rr)) {
+                e.done = true;
+                e.final_status = WD_ERR_NAN;
+            } else if (rr <= q.target2) {
+                e.done = true;
+                e.final_status = WD_OK;
+            } else if (stt == ST_MAXIT || q.iter >= q.maxit) {
+                e.done = true;
+                e.final_status = WD_ERR_NOCONV;
+            } else if (stt == ST_BREAKDOWN) {
+                if (++e.restarts > 2) {
+                    e.done = true;
+                    e.final_status = WD_ERR_BREAKDOWN;
+                } else {
+                    next = ST_SEL2;  // restart with p = r
+                }
+            }
+            if (!e.done && P.mixed && P.mixed_mode == WD_MIXED_DEFECT) next = ST_SEL2;
+            if (e.done) {
+                e.t1 = now_s();
+                active--;
+                q.status = ST_DONE;
+            } else {
+                q.status = next;
+                any_next = any_next || next == ST_SEL1;
+                any_fresh = any_fresh || next == ST_SEL2;
+            }
+        }
+        sys.upload(st);
+        if (any_next) run_sweep(OP_INIT, SFL, InitRel, sys.d(), 1 << ST_SEL1, st, 0);
+        if (any_fresh) run_sweep(OP_INIT, SFL, InitRestart, sys.d(), 1 << ST_SEL2, st, 0);
+    }
+
+    for (auto& e : S)
+        WD_CHECK_HIP(launch_unpack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), 0, 1.0, st, e.g->gm()));
+    sys.download(st);
+    for (int i = 0; i < n; i++) {
+        CgSys& e = S[i];
+        if (e.t1 == 0) e.t1 = now_s();
+        e.iters = sys.h[i].iter;
+        e.true_rel = (e.be2 > 0 && e.rr_true >= 0) ? std::sqrt(e.rr_true / e.be2) : 0.0;
+    }
+}
+
+// CG-M in FP64 for all shifts at once; the base is the smallest shift (the slowest to converge),
+// the others are frozen once their residual |zeta| |r| meets the tolerance.
+static wd_status cgm_solve(wd_gauge* g, double kappa, int n, const double* sigmas, double* const* x, const double* b,
+                           const wd_solver_params& P, wd_solver_stats* stats, hipStream_t st, int poll)
+{
+    const double t0 = now_s();
+    int base = 0;
+    for (int i = 1; i < n; i++)
+        if (sigmas[i] < sigmas[base]) base = i;
+    const double a = 1.0 / (2.0 * kappa), a2 = a * a, s0 = sigmas[base];
+    const int ns = n - 1;
+    std::vector<int> shift_of(n, -1), sys_of_shift;
+    for (int i = 0; i < n; i++)
+        if (i != base) {
+            shift_of[i] = (int)sys_of_shift.size();
+            sys_of_shift.push_back(i);
+        }
+    const Geo& geo = g->geo;
+    const int L64 = g->f64_links();
+    g->ensure_slinks(L64, st);
+    Field B = g->field("cgm.B", SF64, 2);
+    std::vector<Field> X(n), PS(ns);
+    for (int i = 0; i < n; i++) X[i] = g->field("cgm.X" + std::to_string(i), SF64, 2);
+    for (int k = 0; k < ns; k++) PS[k] = g->field("cgm.P" + std::to_string(k), SF64, 1);
+    Field R = g->field("cgm.r", SF64, 1), Pb = g->field("cgm.p", SF64, 1), Tm = g->field("cgm.t", SF64, 1);
+    Field Vm = g->field("cgm.v", SF64, 1), Wm = g->field("cgm.w", SF64, 1);
+    for (int i = 0; i < n; i++) WD_CHECK_HIP(hipMemsetAsync(X[i].base(), 0, X[i].mem->bytes, st));
+    WD_CHECK_HIP(launch_pack_spinor(SF64, b, geo, B.half(0), B.half(1), 0, 1.0, st, g->gm()));
+
+    SysArray sys;
+    sys.alloc(1, g->raw["cgm.sys"]);
+    SysState& q = sys.h[0];
+    std::memset(&q, 0, sizeof(q));
+    q.partials = (double*)g->rawbuf("cgm.partials", sizeof(double) * NRED * (2 * geo.stride / BLOCK + 1));
+    q.maxit = P.max_iter;
+    q.nshift = ns;
+    q.target2 = -1;
+    q.cga_prev = 1.0;
+    std::vector<ShiftScal> sh(std::max(ns, 1));
+    std::vector<SpinorRef> shv(2 * std::max(ns, 1));
+    for (int k = 0; k < ns; k++) {
+        ShiftScal& z = sh[k];
+        std::memset(&z, 0, sizeof(z));
+        z.sigma = sigmas[sys_of_shift[k]] - s0;
+        z.zeta_prev = z.zeta = make_double2(1.0, 0.0);
+        z.active = 1;
+        shv[2 * k] = X[sys_of_shift[k]].half(0);
+        shv[2 * k + 1] = PS[k].all();
+    }
+    ShiftScal* d_sh = (ShiftScal*)g->rawbuf("cgm.sh", sizeof(ShiftScal) * sh.size());
+    SpinorRef* d_shv = (SpinorRef*)g->rawbuf("cgm.shv", sizeof(SpinorRef) * shv.size());
+    {
+        const size_t n1 = sizeof(ShiftScal) * sh.size(), n2 = sizeof(SpinorRef) * shv.size();
+        char* stg = stage_alloc(n1 + n2);
+        std::memcpy(stg, sh.data(), n1);
+        std::memcpy(stg + n1, shv.data(), n2);
+        WD_CHECK_HIP(hipMemcpyAsync(d_sh, stg, n1, hipMemcpyHostToDevice, st));
+        WD_CHECK_HIP(hipMemcpyAsync(d_shv, stg + n1, n2, hipMemcpyHostToDevice, st));
+    }
+    q.sh = d_sh;
+    q.shv = d_shv;
+    sys.upload(st);
+
+    const long nh = R.nsites();
+    JobTable<SweepJob> Init, SX, SP;
+    SweepJob j = sweep_job(0, nh);
+    // r = p = b_e, x = 0, x^s = 0, p^s = b_e, |b_e|^2
+    j.f[R_F0] = R.all();
+    j.f[R_F1] = B.half(0);
+    j.f[R_F2] = Pb.all();
+    j.f[R_F3] = Pb.all();
+    j.f[R_F4] = X[base].half(0);
+    Init.host.push_back(j);
+    j = sweep_job(0, nh);
+    j.f[R_F0] = X[base].half(0);
+    j.f[R_F1] = Pb.all();
+    j.f[R_F2] = R.all();
+    j.f[R_F3] = Wm.all();
+    SX.host.push_back(j);
+    j = sweep_job(0, nh);
+    j.f[R_F0] = Pb.all();
+    j.f[R_F1] = R.all();
+    SP.host.push_back(j);
+    JobTable<HopJob> H1, H2, H3, H4;
+    {
+        const void* d0 = g->slk(L64, 0);
+        const void* d1 = g->slk(L64, 1);
+        const long lcs = g->lcs();
+        HopJob h = hop_job(geo, 1, 0, Pb.all(), Tm.all(), d1, lcs, 1.0);
+        h.tg = g->tg;
+        H1.host.push_back(h);
+        h = hop_job(geo, 0, 0, Tm.all(), Vm.all(), d0, lcs, -0.25);
+        h.tg = g->tg;
+        h.x0 = Pb.all();
+        h.c0 = a2;
+        H2.host.push_back(h);
+        H3.host.push_back(hop_job(geo, 1, 0, Vm.all(), Tm.all(), d1, lcs, 1.0));
+        h = hop_job(geo, 0, 0, Tm.all(), Wm.all(), d0, lcs, -0.25);
+        h.x0 = Vm.all();
+        h.c0 = a2;
+        h.x1 = Pb.all();
+        h.c1 = s0;
+        h.z = Pb.all();
+        H4.host.push_back(h);
+    }
+    const int tz64 = tune_tile(g, SF64, L64, st);
+    for (auto* t : {&H1, &H2, &H3, &H4}) {
+        for (auto& h : t->host) set_tile(h, tz64);
+        layout(*t);
+    }
+    for (auto* t : {&Init, &SX, &SP}) layout(*t);
+    upload_tables(st, g->raw["cgm.tables"], {&Init, &SX, &SP, &H1, &H2, &H3, &H4});
+    run_sweep(OP_MSINIT, SF64, Init, sys.d(), 0, st, 0);
+    sys.download(st);
+    const double bb = sys.h[0].red[2];
+    sys.h[0].target2 = P.tol * P.tol * bb;
+    sys.h[0].shift_target2 = P.tol * P.tol * bb;
+    sys.h[0].cga_prev = 1.0;
+    sys.h[0].cgb = 0.0;
+    if (bb == 0.0) sys.h[0].status = ST_CONVERGED;
+    sys.upload(st);
+
+    const double bH = hop_bytes(H1, SF64, L64, 0);
+    auto iterate = [&](int active_shifts, hipStream_t qs) {
+        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, H1, sys.d(), GATE_RUN, qs, bH);
+        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, H2, sys.d(), GATE_RUN, qs, bH + nh * 192.0);
+        run_hop(SF64, L64, true, RED_NONE, FIN_STORE, H3, sys.d(), GATE_RUN, qs, bH);
+        run_hop(SF64, L64, true, RED_ZDOT, FIN_CGA, H4, sys.d(), GATE_RUN, qs, bH + nh * 2 * 192.0);
+        run_sweep(OP_CGX, SF64, SX, sys.d(), GATE_RUN, qs, sweep_bytes(SX, 6 * 192));
+        run_sweep(ns > 0 ? OP_CGPM : OP_CGP, SF64, SP, sys.d(), GATE_RUN, qs,
+                  sweep_bytes(SP, 3 * 192 + 4 * 192 * active_shifts));
+    };
+    std::shared_ptr<ChunkGraph> graph;
+    if (graphs_on())
+        graph = cached_graph(g, launch_key("cgm", poll, ns, 0, sys.d(), H1, H2, H3, H4, SX, SP), [&](hipStream_t qs) {
+            for (int k = 0; k < poll; k++) iterate(ns, qs);
+        });
+    auto fetch_shifts = [&]() {
+        if (ns == 0) return;
+        const size_t n1 = sizeof(ShiftScal) * ns;
+        void* stg = pinned(n1);
+        WD_CHECK_HIP(hipMemcpyAsync(stg, d_sh, n1, hipMemcpyDeviceToHost, st));
+        WD_CHECK_HIP(hipStreamSynchronize(st));
+        std::memcpy(sh.data(), stg, n1);
+    };
+    int active_shifts = ns;
+    long host_iters = 0;
+    const long host_cap = (long)P.max_iter + 16L * poll + 64;
+    while (sys.h[0].status == ST_RUNNING && host_iters <= host_cap) {
+        if (graph) graph->launch(st);
+        else
+            for (int k = 0; k < poll; k++) iterate(active_shifts, st);
+        host_iters += poll;
+        sys.download(st);
+        fetch_shifts();
+        active_shifts = 0;
+        for (int k = 0; k < ns; k++) active_shifts += sh[k].active;
+    }
+    int status;
+    switch (sys.h[0].status) {
+    case ST_CONVERGED: status = WD_OK; break;
+    case ST_MAXIT: status = WD_ERR_NOCONV; break;
+    case ST_BREAKDOWN: status = WD_ERR_BREAKDOWN; break;
+    case ST_NAN: status = WD_ERR_NAN; break;
+    default: status = WD_ERR_NOCONV;
+    }
+    fetch_shifts();
+    const int iters = sys.h[0].iter;
+    const double t1 = now_s();
+
+    // true residual b_e - (A + sigma_i) x_i of every system, one launch per step for all of them
+    // (one reduction group per system; the residual fields are not kept), then unpack
+    {
+        const size_t pstride = (size_t)NRED * (2 * geo.stride / BLOCK + 1);
+        SysArray rs;
+        rs.alloc(n, g->raw["cgm.rsys"]);
+        double* rpart = (double*)g->rawbuf("cgm.rpartials", sizeof(double) * pstride * n);
+        for (int i = 0; i < n; i++) {
+            std::memset(&rs.h[i], 0, sizeof(SysState));
+            rs.h[i].partials = rpart + pstride * i;
+        }
+        std::vector<Field> RT(n), RV(n), RR(n);
+        for (int i = 0; i < n; i++) {
+            RT[i] = g->field("cgm.RT" + std::to_string(i), SF64, 1);
+            RV[i] = g->field("cgm.RV" + std::to_string(i), SF64, 1);
+            RR[i] = g->field("cgm.RR" + std::to_string(i), SF64, 1);
+        }
+        JobTable<SweepJob> Bs;
+        JobTable<HopJob> Q1, Q2, Q3, Q4;
+        const void* d0 = g->slk(L64, 0);
+        const void* d1 = g->slk(L64, 1);
+        const long lcs = g->lcs();
+        for (int i = 0; i < n; i++) {
+            SweepJob sj = sweep_job(i, nh);
+            sj.f[R_F0] = RR[i].all();
+            sj.f[R_F1] = B.half(0);
+            sj.f[R_F2] = X[i].half(0);
+            sj.c[0] = 1.0;
+            sj.c[1] = -sigmas[i];
+            Bs.host.push_back(sj);
+            HopJob h = hop_job(geo, 1, i, X[i].half(0), RT[i].all(), d1, lcs, 1.0);
+            h.tg = g->tg;
+            Q1.host.push_back(h);
+            h = hop_job(geo, 0, i, RT[i].all(), RV[i].all(), d0, lcs, -0.25);
+            h.tg = g->tg;
+            h.x0 = X[i].half(0);
+            h.c0 = a2;
+            Q2.host.push_back(h);
+            Q3.host.push_back(hop_job(geo, 1, i, RV[i].all(), RT[i].all(), d1, lcs, 1.0));
+            h = hop_job(geo, 0, i, RT[i].all(), RR[i].all(), d0, lcs, 0.25);
+            h.x0 = RR[i].all();
+            h.c0 = 1.0;
+            h.x1 = RV[i].all();
+            h.c1 = -a2;
+            Q4.host.push_back(h);
+        }
+        for (auto* t : {&Q1, &Q2, &Q3, &Q4}) {
+            for (auto& h : t->host) set_tile(h, tz64);
+            layout(*t);
+        }
+        layout(Bs);
+        upload_tables(st, g->raw["cgm.rtables"], {&Bs, &Q1, &Q2, &Q3, &Q4});
+        rs.upload(st);
+        run_sweep(OP_AXPY, SF64, Bs, rs.d(), 0, st, 0);
+        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Q1, rs.d(), 0, st, 0);
+        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Q2, rs.d(), 0, st, 0);
+        run_hop(SF64, L64, true, RED_NONE, FIN_STORE, Q3, rs.d(), 0, st, 0);
+        run_hop(SF64, L64, true, RED_NORM, FIN_STORE, Q4, rs.d(), 0, st, 0);
+        for (int i = 0; i < n; i++)
+            WD_CHECK_HIP(launch_unpack_spinor(SF64, x[i], geo, X[i].half(0), X[i].half(1), 0, 1.0, st, g->gm()));
+        rs.download(st);
+        if (stats)
+            for (int i = 0; i < n; i++) {
+                stats[i].iters = i == base ? iters : (sh[shift_of[i]].active ? iters : sh[shift_of[i]].conv_iter);
+                stats[i].reliable_updates = 0;
+                stats[i].true_rel_res = bb > 0 ? std::sqrt(rs.h[i].red[2] / bb) : 0.0;
+                stats[i].status = status;
+                stats[i].seconds = t1 - t0;
+            }
+    }
+    return (wd_status)status;
+}
+
+wd_status solve_normal(wd_gauge* g, double kappa, int n, const double* sigmas, double* const* x, const double* b,
+                       int method, int guess, const wd_solver_params& P, wd_solver_stats* stats, hipStream_t st)
+{
+    WD_REQUIRE(n >= 1 && n <= 32, "number of shifts must be in 1..32");
+    WD_REQUIRE(kappa > 0, "kappa must be positive");
+    for (int i = 0; i < n; i++) WD_REQUIRE(std::isfinite(sigmas[i]) && sigmas[i] >= 0, "shifts must be >= 0");
+    WD_REQUIRE(P.dagger == 0, "the normal equations take dagger = 0");
+    WD_REQUIRE(guess == WD_GUESS_NONE || guess == WD_GUESS_POLY, "normal equations: guess must be NONE or POLY");
+    if (method == WD_METHOD_MULTISHIFT) return cgm_solve(g, kappa, n, sigmas, x, b, P, stats, st, kPoll);
+    WD_REQUIRE(method == WD_METHOD_SEQUENTIAL || method == WD_METHOD_BATCHED, "unknown method");
+    auto fill = [&](int i, const CgSys& e, wd_status& worst) {
+        if (stats) {
+            stats[i].iters = e.iters;
+            stats[i].reliable_updates = e.reliable;
+            stats[i].status = e.final_status;
+            stats[i].true_rel_res = e.true_rel;
+            stats[i].seconds = e.t1 - e.t0;
+        }
+        if (e.final_status != WD_OK && worst == WD_OK) worst = (wd_status)e.final_status;
+    };
+    EoSource src;
+    prepare_source(g, "nm.", b, 0, src, st);
+    wd_status worst = WD_OK;
+    auto make = [&](int i) {
+        CgSys e;
+        e.g = g;
+        e.kappa = kappa;
+        e.sigma = sigmas[i];
+        e.b = b;
+        e.x = x[i];
+        e.src = src;
+        return e;
+    };
+    if (method == WD_METHOD_BATCHED) {
+        // all shifts iterate together, one launch per solver step (no start guesses)
+        std::vector<CgSys> S;
+        for (int i = 0; i < n; i++) {
+            S.push_back(make(i));
+            S.back().slot = i;
+        }
+        cg_solve(S, P, st, kPoll);
+        for (int i = 0; i < n; i++) fill(i, S[i], worst);
+        return worst;
+    }
+    // largest shift (best conditioned) first; each start vector is the Lagrange extrapolation in
+    // sigma of the solutions found so far (the analogue of Sec. 6.2.1 and Sec. 7)
+    std::vector<int> order(n);
+    for (int i = 0; i < n; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return sigmas[p] > sigmas[q]; });
+    std::vector<Field> X(n);
+    for (int i = 0; i < n; i++) X[i] = g->field("nm.X" + std::to_string(i), SF64, 2);
+    SysState* dummy = (SysState*)g->rawbuf("apply.sys", sizeof(SysState));
+    std::vector<int> done;
+    double be2 = -1;
+    for (int idx : order) {
+        CgSys e = make(idx);
+        e.slot = 0;
+        e.X64 = X[idx];
+        e.be2 = be2;
+        const int kall = (int)done.size();
+        const int k = P.guess_order > 0 ? std::min(P.guess_order, kall) : kall;
+        const int j_first = kall - k;
+        if (guess == WD_GUESS_POLY && k > 0) {
+            // Lagrange weights over the distinct shifts among the previous ones (the latest
+            // solution of a repeated shift); a shift solved before is its own guess
+            const double s = sigmas[idx];
+            std::vector<bool> use(k, true);
+            int same = -1;
+            for (int jj = 0; jj < k; jj++) {
+                const double sj = sigmas[done[j_first + jj]];
+                for (int ii = jj + 1; ii < k; ii++)
+                    if (sigmas[done[j_first + ii]] == sj) use[jj] = false;
+                if (use[jj] && sj == s) same = jj;
+            }
+            std::vector<double> c(k, 0.0);
+            for (int jj = 0; jj < k; jj++) {
+                if (same >= 0) c[jj] = jj == same ? 1.0 : 0.0;
+                else if (use[jj]) {
+                    const double sj = sigmas[done[j_first + jj]];
+                    double w = 1.0;
+                    for (int ii = 0; ii < k; ii++) {
+                        if (ii == jj || !use[ii]) continue;
+                        const double si = sigmas[done[j_first + ii]];
+                        w *= (s - si) / (sj - si);
+                    }
+                    c[jj] = w;
+                }
+            }
+            // x0 = sum_j c_j x_j over the even half (7 inputs per sweep), zero odd half
+            WD_CHECK_HIP(hipMemsetAsync(X[idx].base(), 0, X[idx].mem->bytes, st));
+            for (int j0 = 0; j0 < k; j0 += 7) {
+                JobTable<SweepJob> L;
+                SweepJob sj = sweep_job(0, X[idx].stride);
+                sj.f[R_F0] = X[idx].half(0);
+                const int mc = std::min(7, k - j0);
+                for (int jj = 0; jj < mc; jj++) {
+                    sj.f[1 + jj] = X[done[j_first + j0 + jj]].half(0);
+                    sj.c[jj] = c[j0 + jj];
+                }
+                sj.flags = (mc << 8) | (j0 > 0 ? 1 : 0);
+                L.host.push_back(sj);
+                layout(L);
+                upload_tables(st, g->raw["nm.tables"], {&L});
+                run_sweep(OP_LINCOMB, SF64, L, dummy, 0, st, sweep_bytes(L, (mc + 1 + (j0 > 0)) * 192.0));
+            }
+            e.x_ready = true;
+        }
+        std::vector<CgSys> S{e};
+        cg_solve(S, P, st, kPoll);
+        be2 = S[0].be2;
+        fill(idx, S[0], worst);
+        done.push_back(idx);
+    }
+    return worst;
+}
+
 } // namespace wd

@@ -41,6 +41,9 @@ enum Fin {
     FIN_ALPHA = 3,   // delta' = <rhat, r>, |r|^2, alpha    (+ shifted alpha, freezing)
     FIN_END = 4,     // end of iteration: commit status     (+ rotate shifted scalars)
     FIN_RESTART = 5, // new residual: delta = <rhat, r>, |r|^2, status RUNNING
+    FIN_CGA = 6,     // CG: alpha = |r|^2 / <p, A p>                (+ shifted zeta, alpha)
+    FIN_CGB = 7,     // CG: beta = |r_new|^2 / |r|^2, status     (+ shifted beta, freezing)
+    FIN_CGEND = 8,   // CG-M end of iteration: commit status, rotate the shifted zeta
 };
 
 struct ShiftScal {
@@ -70,10 +73,11 @@ struct SysState {
     double target2;    // stop when rr <= target2
     double delta_rel2; // reliable update when rr < delta_rel2 * maxrr
     double shift_target2;
+    double cga, cga_prev, cgb;  // CG: alpha_n, alpha_{n-1}, beta_n
     double red[NRED];  // last reduced sums
     double* partials;  // [max blocks][NRED]
     ShiftScal* sh;     // [nshift]
-    SpinorRef* shv;    // [2 * nshift]: x_sigma, s_sigma
+    SpinorRef* shv;    // [2 * nshift]: x_sigma, s_sigma (BiCGstab-M) or x_sigma, p_sigma (CG-M)
 };
 
 // one entry per system of a launch: which partial sums the finisher adds
