@@ -147,6 +147,35 @@ def committed_traffic():
     return float(m.group(1)) if sha.hexdigest() == h.group(1) else None
 
 
+def normal_equations(torch, wd, np, g, bd, kappa, W, reps):
+    """CG and CG-M (named in Sec. 8 as the Krylov pair the findings should carry over to) on the
+    shifted even-site normal equations of the benchmark lattice at its lightest mass:
+    (M_prec^dag M_prec + sigma_i) x_i = b_e for the 8 shifts 0, 25, 50, ..., 1600 (the spectrum of
+    M_prec^dag M_prec lies near (1/(2 kappa))^4 ~ 190 here). CG-M in FP64 against single-shift
+    mixed-precision CG run once per shift (largest first, Lagrange guess in sigma) or batched."""
+    sig = [0.0] + [25.0 * 2 ** k for k in range(7)]
+    xs = [torch.zeros_like(bd) for _ in sig]
+    pm = wd.params(tol=1e-8, spinor=W["spinor"], links=W["links"], delta=W["delta"])
+    runs = {"cg_m_fp64": dict(method=wd.WD_METHOD_MULTISHIFT, p=wd.params(tol=1e-8, mixed=False)),
+            "cg_sequential_mixed": dict(method=wd.WD_METHOD_SEQUENTIAL, p=pm),
+            "cg_batched_mixed": dict(method=wd.WD_METHOD_BATCHED, p=pm)}
+    out = {"kappa": kappa, "sigmas": sig}
+    for name, kw in runs.items():
+        ts = []
+        for rep in range(reps + 1):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            _, st = wd.wd_normal_solve(g, kappa, sig, bd, xs=xs, **kw)
+            torch.cuda.synchronize()
+            if rep > 0:
+                ts.append(time.perf_counter() - a)
+        out[name] = {"solve_s": round(float(np.median(ts)), 5), "iters": [s["iters"] for s in st],
+                     "reliable_updates": [s["reliable_updates"] for s in st],
+                     "max_true_rel_res": float(f"{max(s['true_rel_res'] for s in st):.3e}")}
+    out["speedup_sequential_vs_cg_m"] = round(out["cg_m_fp64"]["solve_s"] / out["cg_sequential_mixed"]["solve_s"], 3)
+    return out
+
+
 def other_configs(torch, dev, wd, li, np, reps):
     """The batched and the differentiation workloads, timed beside the step.
 
@@ -335,6 +364,7 @@ def main():
         return round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 else None
 
     hop_ms, hop_n, hop_bytes = seq[0]
+    normal = normal_equations(torch, wd, np, g, bd, kappas[-1], W, args.steps)
     dev_bytes = g.device_bytes()
     g.close()
 
@@ -448,6 +478,7 @@ def main():
                           "note": "the paper's figures (Sec. 4, Table 3); other hardware and workload; "
                                   "effective = the paper's no-reuse byte count"},
         "temporal_gauge": temporal,
+        "normal_equations_cg": normal,
         "batched_96_systems": extra["batched"],
         "differentiation_16x32": extra["grad"],
         "device_bytes": dev_bytes,

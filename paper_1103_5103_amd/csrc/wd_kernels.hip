@@ -626,7 +626,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
         }
 
     } else if constexpr (OP == OP_INIT) {
-        // r_lo = r_hi; optionally rhat = r_lo, s = r_lo, x_lo = 0; then <rhat, r_lo>, |r_lo|^2
+        // r_lo = r_hi; optionally rhat = r_lo, s = r_lo (flags 1, 2), x_lo = 0 (flags 4); CG (flags 8):
+        // p = r_lo + beta p with the beta the host set in the record; then <rhat, r_lo>, |r_lo|^2
         if (ok) {
             cx<T> r[12];
             {
@@ -640,6 +641,14 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
             load_spinor<SFL, T>(J.f[R_F0], i, r);
             if (J.flags & 1) store_spinor<SFL, T>(J.f[R_F2], i, r);
             if (J.flags & 2) store_spinor<SFL, T>(J.f[R_F3], i, r);
+            if (J.flags & 8) {
+                const T bt = (T)S->cgb;
+                cx<T> pp[12];
+                load_spinor<SFL, T>(J.f[R_F3], i, pp);
+#pragma unroll
+                for (int k = 0; k < 12; k++) pp[k] = r[k] + bt * pp[k];
+                store_spinor<SFL, T>(J.f[R_F3], i, pp);
+            }
             if (J.flags & 4) {
                 cx<T> zero[12];
 #pragma unroll

@@ -1425,7 +1425,7 @@ static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream
         sj.f[R_F4] = e.xl.all();
         sj.flags = 2 | 4;
         InitFirst.host.push_back(sj);
-        sj.flags = 0;
+        sj.flags = 8;  // p = r + beta' p (beta' set by the host)
         InitRel.host.push_back(sj);
         sj.flags = 2;
         InitRestart.host.push_back(sj);
@@ -1531,11 +1531,12 @@ static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream
                              [&](hipStream_t q) {
                                  for (int k = 0; k < poll; k++) iterate(q);
                              });
-    // Reliable update of the systems that stopped (gate GATE_STOPPED): the p update of the
-    // iteration in which a system stopped was gated off; a continuing reliable update keeps p, so
-    // apply it first (defect correction restarts with p = r instead)
+    // Reliable update of the systems that stopped (gate GATE_STOPPED). The p update of the
+    // iteration in which a system stopped was gated off, so p is still p_n; a continuing system
+    // takes the new search direction from the true residual, p = r_true + (|r_true|^2 / |r_n|^2) p_n,
+    // as if the iteration had produced r_true (keeping p_{n+1} = r_iter + beta p_n instead makes
+    // alpha overshoot once the true residual exceeds the iterated one, and the iteration diverges)
     auto reliable_update = [&]() {
-        if (!(P.mixed && P.mixed_mode == WD_MIXED_DEFECT)) run_sweep(OP_CGP, SFL, SP, sys.d(), GATE_STOPPED, st, bSP);
         run_sweep(OP_ACC, SFL, Acc, sys.d(), GATE_STOPPED, st, sweep_bytes(Acc, 2 * 192 + 2 * bx));
         residual(GATE_STOPPED);
     };
@@ -1584,7 +1585,11 @@ static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream
             e.reliable++;
             const double rr = q.red[2];
             e.rr_true = rr;
-            int next = ST_SEL1;  // continue: keep p
+            // continue (p from the true residual) while the true residual stays within a factor 2 in
+            // |r|^2 of the iterated one (q.rr); otherwise, and after a failed exit check (the
+            // iterated residual met the tolerance, the true one did not), restart with p = r
+            int next = (stt == ST_RELIABLE && rr <= 2.0 * q.rr && q.rr > 0 && q.cgb > 0) ? ST_SEL1 : ST_SEL2;
+            if (next == ST_SEL1) q.cgb = rr * q.cgb / q.rr;  // |r_true|^2 / |r_n|^2, |r_n|^2 = q.rr / q.cgb
             if (!std::isfinite(rr)) {
                 e.done = true;
                 e.final_status = WD_ERR_NAN;

@@ -70,6 +70,27 @@ def test_multishift_full_size(big):
         assert res < 1e-8
 
 
+def test_normal_equations_full_size(big):
+    """CG-M and the sequential mixed CG on the 32^3x64 lattice, kappa 0.134, the 8 shifts the
+    benchmark uses: the oracle's FP64 residual |b_e - (A + sigma) x| / |b_e| of the smallest and
+    the largest shift of each method, and the two methods' solutions agree."""
+    dims, U, b, g = big
+    kappa = 0.134
+    sig = [0.0] + [25.0 * 2 ** k for k in range(7)]
+    be = oracle.even_part(b)
+    xm, sm = wd.wd_normal_solve(g, kappa, sig, _t(b), method=wd.WD_METHOD_MULTISHIFT, p=wd.params(tol=1e-8, mixed=False))
+    xq, sq = wd.wd_normal_solve(g, kappa, sig, _t(b), p=wd.params(tol=1e-8, spinor="f32", links="f16", delta=1e-3))
+    for i in (0, 7):
+        for xs, sts, name in ((xm, sm, "cg-m"), (xq, sq, "cg seq")):
+            x = _n(xs[i])
+            res = np.linalg.norm(be - oracle.normal_apply(U, kappa, sig[i], x)) / np.linalg.norm(be)
+            _say("32^3x64", name, sig[i], sts[i], "oracle residual", res)
+            assert res < 1.5e-8
+            assert abs(sts[i]["true_rel_res"] - res) < 0.05 * res
+        d = _n(xm[i]) - _n(xq[i])
+        assert np.linalg.norm(d) / np.linalg.norm(_n(xm[i])) < 4e-7
+
+
 def test_multimass_16x32_fp64_vs_mixed():
     """16^3x32, 6 masses: BiCGstab-M (FP64) and sequential even-odd mixed BiCGstab with FP16
     spinors and links, both to 1e-8 for every mass."""

@@ -151,3 +151,23 @@ def test_cg_rejects_bad_arguments():
     with pytest.raises(wd.WdError):
         wd.wd_normal_solve(g, 0.12, [1.0], b, p=wd.params(dagger=True))
     g.close()
+
+
+@pytest.mark.parametrize("delta", [1e-4, 1e-5])
+def test_cg_small_reliable_delta(delta):
+    """Reliable updates far apart: the low-precision iterated residual falls below what the FP16
+    operator resolves, so at an update the true residual exceeds the iterated one; the solver
+    then restarts or rebuilds p from the true residual and still converges."""
+    dims = (8, 8, 8, 8)
+    U = li.random_links(dims, 1.0, 1307)
+    b = li.gaussian_field(dims, 2307)
+    kappa, tol = 0.134, 1e-8
+    sig = [0.0, 100.0, 1600.0]
+    g = wd.wd_gauge_create(_t(U))
+    for m in (wd.WD_METHOD_SEQUENTIAL, wd.WD_METHOD_BATCHED):
+        xs, sts = wd.wd_normal_solve(g, kappa, sig, _t(b), method=m,
+                                     p=wd.params(tol=tol, spinor="f32", links="f16", delta=delta))
+        _say("delta", delta, "method", m, [s["iters"] for s in sts], [s["reliable_updates"] for s in sts])
+        _check(U, kappa, sig, b, xs, sts, tol)
+        assert max(s["iters"] for s in sts) < 60
+    g.close()
