@@ -292,7 +292,6 @@ struct HopIn {
     const SpinorRef& in;
     const Stg<SF, STG>& L;
     int base, nsl;
-    bool nt;  // non-temporal link loads (links not shared with other systems of the launch)
     bool tg;  // temporal gauge: unit time links inside the lattice
 };
 
@@ -380,8 +379,8 @@ __device__ __forceinline__ void group_barrier(cx<T> acc[12], int& dep)
 }
 
 // Both directions of axis MU; the two links are loaded together (one 16-byte load per chunk for
-// the paired 16-bit formats). G = directions per ordering group.
-template <int MU, int G, bool DAG, int SFI, int LF, bool STG, class T>
+// the paired 16-bit formats). G = directions per ordering group. NTL: non-temporal link loads.
+template <int MU, int G, bool DAG, int SFI, int LF, bool STG, bool NTL, class T>
 __device__ __forceinline__ void hop_axis(const Geo& g, int cb, int x, int y, int z, int t, const HopIn<SFI, STG>& in,
                                          const void* links, long lcs, cx<T> acc[12], int& dep)
 {
@@ -390,8 +389,7 @@ __device__ __forceinline__ void hop_axis(const Geo& g, int cb, int x, int y, int
     const bool unit_f = MU == 3 && in.tg && t != g.T - 1;
     const bool unit_b = MU == 3 && in.tg && t != 0;
     if (!(unit_f && unit_b)) {
-        if (in.nt) load_link_pair<LF, T, true>(links, lcs, MU, cb + dep, Wf, Wb);
-        else load_link_pair<LF, T, false>(links, lcs, MU, cb + dep, Wf, Wb);
+        load_link_pair<LF, T, NTL>(links, lcs, MU, cb + dep, Wf, Wb);
     }
     hop_dir<MU, 0, DAG, SFI, STG, T>(g, cb, x, y, z, t, in, Wf, acc, dep, unit_f);
     group_barrier<2 * MU, G>(acc, dep);
@@ -399,7 +397,7 @@ __device__ __forceinline__ void hop_axis(const Geo& g, int cb, int x, int y, int
     group_barrier<2 * MU + 1, G>(acc, dep);
 }
 
-template <bool DAG, int SFI, int LF, bool STG, class T>
+template <bool DAG, int SFI, int LF, bool STG, bool NTL, class T>
 __device__ __forceinline__ void hop_site(const Geo& g, int p, int cb, const HopIn<SFI, STG>& in, const void* links,
                                          long lcs, cx<T> acc[12])
 {
@@ -409,10 +407,10 @@ __device__ __forceinline__ void hop_site(const Geo& g, int p, int cb, const HopI
 #pragma unroll
     for (int k = 0; k < 12; k++) acc[k] = mk<T>(T(0), T(0));
     int dep = 0;
-    hop_axis<0, G, DAG, SFI, LF, STG, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    hop_axis<1, G, DAG, SFI, LF, STG, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    hop_axis<2, G, DAG, SFI, LF, STG, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    hop_axis<3, G, DAG, SFI, LF, STG, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    hop_axis<0, G, DAG, SFI, LF, STG, NTL, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    hop_axis<1, G, DAG, SFI, LF, STG, NTL, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    hop_axis<2, G, DAG, SFI, LF, STG, NTL, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
+    hop_axis<3, G, DAG, SFI, LF, STG, NTL, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
 }
 
 template <int SF> struct HopWaves { static constexpr int W = WD_HOP_WAVES_LO; };
@@ -433,8 +431,11 @@ __device__ __forceinline__ int tiled_block(const HopJob& J, int lb)
     return q + J.bpp * ((zg * J.tz + zz) + J.g.Z * t);
 }
 
-// TG: some job of the launch has temporal-gauge links (TG = false compiles the unit-link paths out)
-template <int SF, int LF, bool DAG, int RED, int FIN, bool STG, bool TG>
+// TG: some job of the launch has temporal-gauge links (TG = false compiles the unit-link paths out).
+// NTL: the links are loaded non-temporally, so that they do not evict the neighbour spinors from
+// L2; launches with interleaved systems (links shared through L2) take ordinary loads. A compile-
+// time choice: as a run-time branch the compiler merges the two identical loads and drops the hint.
+template <int SF, int LF, bool DAG, int RED, int FIN, bool STG, bool NTL, bool TG>
 __global__ __launch_bounds__(BLOCK, HopWaves<SF>::W > 0 ? HopWaves<SF>::W : 1) void k_hop(
     const HopJob* __restrict__ jobs, int njobs, SysState* __restrict__ sys, int gated, int* exec)
 {
@@ -466,11 +467,11 @@ __global__ __launch_bounds__(BLOCK, HopWaves<SF>::W > 0 ? HopWaves<SF>::W : 1) v
         }
         __syncthreads();
     }
-    const HopIn<SF, STG> hin{J.in, stg, base, nsl, J.ilv <= 1, TG && J.tg != 0};
+    const HopIn<SF, STG> hin{J.in, stg, base, nsl, TG && J.tg != 0};
     double v[NRED] = {0.0, 0.0, 0.0, 0.0};
     if (cb < J.g.Vh) {
         cx<T> acc[12];
-        hop_site<DAG, SF, LF, STG, T>(J.g, J.parity, cb, hin, J.links, J.lcs, acc);
+        hop_site<DAG, SF, LF, STG, NTL, T>(J.g, J.parity, cb, hin, J.links, J.lcs, acc);
         const T c2 = (T)J.c2;
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[k] = c2 * acc[k];
@@ -1221,7 +1222,9 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const double2* __restrict__ xs, 
 static inline dim3 grid1(long nblk) { return dim3((unsigned)nblk); }
 
 #define HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, STG_, TG_)                                                          \
-    hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, STG_, TG_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs, \
+    if (ntl) hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, STG_, true, TG_>), grid1(nblocks), dim3(BLOCK), 0, s, \
+                                jobs, njobs, sys, gated, exec);                                                    \
+    else hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, STG_, false, TG_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs, \
                        sys, gated, exec)
 // The kernel does not depend on the finisher run after it (FIN_ names the instantiation only): the
 // launch is chosen by the reduction kind.
@@ -1267,7 +1270,7 @@ hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState
 }
 
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
-                      SysState* sys, int gated, hipStream_t s, int* exec, int stage, int tg)
+                      SysState* sys, int gated, hipStream_t s, int* exec, int stage, int tg, int ntl)
 {
     if (tg && dag) return hipErrorInvalidValue;  // the adjoint hop runs on the caller's links only
     if (nblocks <= 0) return hipSuccess;

@@ -10,9 +10,11 @@ enum SweepOp { OP_W = 0, OP_XR = 1, OP_S = 2, OP_SHIFT = 3, OP_INIT = 4, OP_ACC 
 
 // exec (may be NULL): incremented once per job that was not gated off. stage: LDS staging of the
 // x/y neighbours in the FP32/FP16 hop (1 on, 0 off, -1 the default of hop_stage_default()).
-// tg: some job has temporal-gauge links (HopJob::tg); must be 0 for the adjoint hop.
+// tg: some job has temporal-gauge links (HopJob::tg); must be 0 for the adjoint hop. ntl:
+// non-temporal link loads (for launches in which no two jobs share links through L2).
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
-                      SysState* sys, int gated, hipStream_t s, int* exec = nullptr, int stage = -1, int tg = 0);
+                      SysState* sys, int gated, hipStream_t s, int* exec = nullptr, int stage = -1, int tg = 0,
+                      int ntl = 1);
 int hop_stage_default();
 int hop_stage64_default();
 hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState* sys, int gated, hipStream_t s);

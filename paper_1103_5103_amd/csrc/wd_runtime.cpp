@@ -248,9 +248,18 @@ void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>&
         b = T.get();
         WD_CHECK_HIP(hipEventRecord(a, s));
     }
-    int tg = 0;
-    for (auto& j : t.host) tg |= j.tg;
-    WD_CHECK_HIP(launch_hop(sf, lf, dag, red, fin, t.d(), t.n(), t.nblocks, sys, gated, s, flag, -1, tg));
+    // Non-temporal link loads keep the links from evicting the neighbour spinors in L2. They pay
+    // off when the links cannot stay in the 256 MB Infinity Cache between hops anyway (more than
+    // 64 MB of links in the launch), and not when interleaved systems read the shared links from L2.
+    int tg = 0, ntl = 1;
+    double link_bytes = 0;
+    for (auto& j : t.host) {
+        tg |= j.tg;
+        if (j.ilv > 1) ntl = 0;
+        link_bytes += (double)j.g.Vh * 8 * link_chunks(lf) * link_chunk_bytes(lf);
+    }
+    if (link_bytes <= 64.0 * (1 << 20)) ntl = 0;
+    WD_CHECK_HIP(launch_hop(sf, lf, dag, red, fin, t.d(), t.n(), t.nblocks, sys, gated, s, flag, -1, tg, ntl));
     if (T.on) {
         WD_CHECK_HIP(hipEventRecord(b, s));
         T.pending.push_back({cls, a, b, bytes, (int)(flag - T.dflags), t.n()});

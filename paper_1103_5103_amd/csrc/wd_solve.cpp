@@ -159,16 +159,26 @@ static HopJob hop_job(const Geo& g, int parity, int sys, const SpinorRef& in, co
                       const void* links, long lcs, double c2);
 template <class J> static void layout(JobTable<J>& t);
 
-int tune_tile(wd_gauge* g, int sf, int lf, hipStream_t st)
+// The link-load policy a launch of this handle's hops takes (run_hop): non-temporal unless systems
+// of the launch share the links through L2 (interleaved) or the links are small enough to stay
+// in the Infinity Cache. The block order is tuned for that policy.
+static int link_policy(wd_gauge* g, int lf, bool shared)
+{
+    const double bytes = (double)g->geo.Vh * 8 * link_chunks(lf) * link_chunk_bytes(lf);
+    return !shared && bytes > 64.0 * (1 << 20);
+}
+
+int tune_tile(wd_gauge* g, int sf, int lf, hipStream_t st, bool shared = false)
 {
     const Geo& G = g->geo;
+    const int ntl = link_policy(g, lf, shared);
     if (const char* env = std::getenv("WD_TILE")) {
         int tz = std::atoi(env);
         return tile_valid(G, tz) ? tz : 0;
     }
     if ((G.Xh * G.Y) % BLOCK != 0 || G.Vh < (1 << 16)) return 0;
     char key[96];
-    std::snprintf(key, sizeof(key), "%d.%d.%d.%d.%d.%d", G.X, G.Y, G.Z, G.T, sf, lf);
+    std::snprintf(key, sizeof(key), "%d.%d.%d.%d.%d.%d.%d", G.X, G.Y, G.Z, G.T, sf, lf, ntl);
     auto it = tile_cache().find(key);
     if (it != tile_cache().end()) return it->second;
     g->ensure_slinks(lf, st);
@@ -189,10 +199,10 @@ int tune_tile(wd_gauge* g, int sf, int lf, hipStream_t st)
         layout(t);
         t.upload(st);
         for (int w = 0; w < 2; w++)
-            WD_CHECK_HIP(launch_hop(sf, lf, false, RED_NONE, FIN_STORE, t.d(), t.n(), t.nblocks, dummy, 0, st, nullptr, -1, j.tg));
+            WD_CHECK_HIP(launch_hop(sf, lf, false, RED_NONE, FIN_STORE, t.d(), t.n(), t.nblocks, dummy, 0, st, nullptr, -1, j.tg, ntl));
         WD_CHECK_HIP(hipEventRecord(e0, st));
         for (int w = 0; w < 6; w++)
-            WD_CHECK_HIP(launch_hop(sf, lf, false, RED_NONE, FIN_STORE, t.d(), t.n(), t.nblocks, dummy, 0, st, nullptr, -1, j.tg));
+            WD_CHECK_HIP(launch_hop(sf, lf, false, RED_NONE, FIN_STORE, t.d(), t.n(), t.nblocks, dummy, 0, st, nullptr, -1, j.tg, ntl));
         WD_CHECK_HIP(hipEventRecord(e1, st));
         WD_CHECK_HIP(hipEventSynchronize(e1));
         float ms = 0;
@@ -386,8 +396,12 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
 
     std::vector<int> tile_lo(n), tile_64(n);
     for (int i = 0; i < n; i++) {
-        tile_lo[i] = tune_tile(S[i].g, SFL, LFL, st);
-        tile_64[i] = tune_tile(S[i].g, SF64, L64, st);
+        // systems on the same gauge field form interleaved groups (links shared through L2)
+        bool shared = false;
+        for (int k = 0; k < n; k++) shared = shared || (k != i && S[k].g == S[i].g);
+        shared = shared && interleave_on();
+        tile_lo[i] = tune_tile(S[i].g, SFL, LFL, st, shared);
+        tile_64[i] = tune_tile(S[i].g, SF64, L64, st, shared);
     }
     for (auto& e : S) {
         e.g->ensure_slinks(LFL, st);
@@ -1330,8 +1344,12 @@ static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream
     const double t_start = now_s();
     std::vector<int> tile_lo(n), tile_64(n);
     for (int i = 0; i < n; i++) {
-        tile_lo[i] = tune_tile(S[i].g, SFL, LFL, st);
-        tile_64[i] = tune_tile(S[i].g, SF64, L64, st);
+        // systems on the same gauge field form interleaved groups (links shared through L2)
+        bool shared = false;
+        for (int k = 0; k < n; k++) shared = shared || (k != i && S[k].g == S[i].g);
+        shared = shared && interleave_on();
+        tile_lo[i] = tune_tile(S[i].g, SFL, LFL, st, shared);
+        tile_64[i] = tune_tile(S[i].g, SF64, L64, st, shared);
     }
     for (auto& e : S) {
         e.g->ensure_slinks(LFL, st);
