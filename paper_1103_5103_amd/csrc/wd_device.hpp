@@ -134,11 +134,12 @@ __device__ __forceinline__ V gld(const void* base, long idx)
     typedef __attribute__((address_space(1))) const V GV;
     return *((GV*)base + idx);
 }
-template <class V>
+template <class V, bool NT = false>
 __device__ __forceinline__ void gst(void* base, long idx, V v)
 {
     typedef __attribute__((address_space(1))) V GV;
-    *((GV*)base + idx) = v;
+    if constexpr (NT) __builtin_nontemporal_store(v, (GV*)base + idx);
+    else *((GV*)base + idx) = v;
 }
 
 // ---------------------------------------------------------------- field views
@@ -178,23 +179,25 @@ __device__ __forceinline__ void load_spinor(const SpinorRef& r, long i, cx<T> v[
     }
 }
 
-template <int SF, class T>
+// NT: non-temporal stores (a hop's output is not read again within the launch)
+template <int SF, class T, bool NT = false>
 __device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const cx<T> v[12])
 {
     if constexpr (SF == SF64) {
 #pragma unroll
-        for (int j = 0; j < 12; j++) gst<d2v>(r.p, chunk_at(12, r.cs, i, j), d2v{(double)v[j].re, (double)v[j].im});
+        for (int j = 0; j < 12; j++)
+            gst<d2v, NT>(r.p, chunk_at(12, r.cs, i, j), d2v{(double)v[j].re, (double)v[j].im});
     } else if constexpr (SF == SF32) {
 #pragma unroll
         for (int j = 0; j < 6; j++)
-            gst<f4v>(r.p, chunk_at(6, r.cs, i, j),
-                     f4v{(float)v[2 * j].re, (float)v[2 * j].im, (float)v[2 * j + 1].re, (float)v[2 * j + 1].im});
+            gst<f4v, NT>(r.p, chunk_at(6, r.cs, i, j),
+                         f4v{(float)v[2 * j].re, (float)v[2 * j].im, (float)v[2 * j + 1].re, (float)v[2 * j + 1].im});
     } else {
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf((float)v[k].re), fabsf((float)v[k].im)));
         const float inv = m > 0.f ? 1.0f / m : 0.f;
-        gst<float>(r.nrm, i, m);
+        gst<float, NT>(r.nrm, i, m);
 #pragma unroll
         for (int j = 0; j < 3; j++) {
             h8 q;
@@ -203,7 +206,7 @@ __device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const c
                 q[2 * k] = (_Float16)((float)v[4 * j + k].re * inv);
                 q[2 * k + 1] = (_Float16)((float)v[4 * j + k].im * inv);
             }
-            gst<h8>(r.p, chunk_at(3, r.cs, i, j), q);
+            gst<h8, NT>(r.p, chunk_at(3, r.cs, i, j), q);
         }
     }
 }

@@ -489,7 +489,7 @@ __global__ __launch_bounds__(BLOCK, HopWaves<SF>::W > 0 ? HopWaves<SF>::W : 1) v
 #pragma unroll
             for (int k = 0; k < 12; k++) acc[k] = acc[k] + c1 * x1[k];
         }
-        store_spinor<SF, T>(J.out, cb, acc);
+        store_spinor<SF, T, NTL>(J.out, cb, acc);
         if constexpr (RED == RED_ZDOT) {
             cx<T> z[12];
             load_spinor<SF, T>(J.z, cb, z);
