@@ -804,6 +804,52 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
     }
 }
 
+// ================================================================ start vector and its residual
+
+// Sequential multi-mass start (Sec. 6.2.1) without applying the operator: for the even-odd system
+// of mass a = 1/(2 kappa), with the earlier solutions x_j and their FP64 residuals
+// r_j = b_prec(a_j) - M_prec(a_j) x_j (b_prec(a) = a b_e + h, M_prec(a) = a^2 - K, K independent
+// of the mass),
+//   x0 = sum_j c_j x_j,
+//   r0 = b_prec(a) - M_prec(a) x0 = cb b_e + ch h + sum_j cx_j x_j + sum_j c_j r_j
+// with cb = a - sum c_j a_j, ch = 1 - sum c_j, cx_j = c_j (a_j^2 - a^2), since K x_j =
+// r_j - a_j b_e - h + a_j^2 x_j. FP64 half fields over n sites; acc = 1 adds to x0 and r0 (inputs
+// in chunks of GUESS_MAX).
+__global__ __launch_bounds__(BLOCK) void k_guess(GuessArgs A)
+{
+    const long i = (long)blockIdx.x * BLOCK + threadIdx.x;
+    if (i >= A.n) return;
+    cx<double> x0[12], r0[12], v[12];
+    if (A.acc) {
+        load_spinor<SF64, double>(A.x0, i, x0);
+        load_spinor<SF64, double>(A.r0, i, r0);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; k++) x0[k] = r0[k] = mk<double>(0.0, 0.0);
+    }
+    if (A.be.p) {
+        load_spinor<SF64, double>(A.be, i, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) r0[k] = r0[k] + A.cb * v[k];
+        load_spinor<SF64, double>(A.h, i, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) r0[k] = r0[k] + A.ch * v[k];
+    }
+    for (int j = 0; j < A.k; j++) {
+        load_spinor<SF64, double>(A.xs[j], i, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            x0[k] = x0[k] + A.c[j] * v[k];
+            r0[k] = r0[k] + A.cx[j] * v[k];
+        }
+        load_spinor<SF64, double>(A.rs[j], i, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) r0[k] = r0[k] + A.c[j] * v[k];
+    }
+    store_spinor<SF64, double>(A.x0, i, x0);
+    store_spinor<SF64, double>(A.r0, i, r0);
+}
+
 // ================================================================ inner products of full fields
 
 // <a, b_j> for j < m (m <= DOTS_MAX) over the real sites of two full FP64 fields in the internal
@@ -1394,6 +1440,13 @@ hipError_t launch_dots(SpinorRef a, const SpinorRef* bs, int m, const Geo& g, do
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dots_finish, dim3(1), dim3(BLOCK), 0, s, partials, nb, m, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_guess(const GuessArgs& a, hipStream_t s)
+{
+    if (a.k < 0 || a.k > GUESS_MAX || a.n <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_guess, grid1((a.n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, a);
     return hipGetLastError();
 }
 

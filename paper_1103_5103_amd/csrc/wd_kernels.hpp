@@ -36,6 +36,18 @@ hipError_t launch_recon_check(const void* lk, int Vh, long lcs, double* blockmax
 // out[2 j], out[2 j + 1] = <a, bs[j]> (j < m <= DOTS_MAX) over the real sites of full FP64 fields;
 // bs: device array of m views; partials: device, >= (2 stride / BLOCK + 1) * 2 * DOTS_MAX doubles
 constexpr int DOTS_MAX = 8;
+// start vector x0 = sum c_j x_j and its even-odd residual from the earlier solutions and their
+// FP64 residuals (no operator application): see k_guess. be.p == nullptr: no b_e / h terms.
+constexpr int GUESS_MAX = 8;
+struct GuessArgs {
+    SpinorRef x0, r0, be, h;
+    SpinorRef xs[GUESS_MAX], rs[GUESS_MAX];
+    double c[GUESS_MAX], cx[GUESS_MAX];
+    double cb, ch;
+    long n;
+    int k, acc;
+};
+hipError_t launch_guess(const GuessArgs& a, hipStream_t s);
 hipError_t launch_dots(SpinorRef a, const SpinorRef* bs, int m, const Geo& g, double* partials, double* out,
                        hipStream_t s);
 hipError_t launch_lincomb(double* out, const double* const* ins, const double* c, int k, long ncomplex, hipStream_t s);

@@ -351,7 +351,9 @@ struct EoSys {
     EoSource src;      // prepared by the caller, or built here
     Field X64;         // FP64 solution (even half iterated, odd half rebuilt); caller-provided or own
     bool x_ready = false;  // X64 already holds the start vector (use_x0 handled by the caller)
-    Field BP, RH, T64;
+    bool r_ready = false;  // RH already holds b_prec - M_prec x0 for that start vector (one system only)
+    Field RH;              // FP64 residual b_prec - M_prec x_e; caller-provided or own
+    Field BP, T64;
     Field r, rh, s, w, As, Aw, tmp, xl;
     bool done = false;
     int restarts = 0, reliable = 0;
@@ -410,7 +412,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         if (!e.src.B64.mem) prepare_source(e.g, k, e.b, P.dagger, e.src, st);
         if (!e.X64.mem) e.X64 = e.g->field(k + "X64", SF64, 2);
         e.BP = e.g->field(k + "BP", SF64, 1);
-        e.RH = e.g->field(k + "RH", SF64, 1);
+        if (!e.RH.mem) e.RH = e.g->field(k + "RH", SF64, 1);
         e.T64 = e.g->field(k + "T64", SF64, 1);
         e.r = e.g->field(k + "r", SFL, 1);
         e.rh = e.g->field(k + "rh", SFL, 1);
@@ -580,7 +582,8 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
             WD_CHECK_HIP(hipMemsetAsync(e.X64.base(), 0, e.X64.mem->bytes, st));
     }
     run_sweep(OP_AXPY, SF64, Bp, sys.d(), 0, st, sweep_bytes(Bp, 3 * 192));
-    if (any_x0) {
+    WD_REQUIRE(n == 1 || !S[0].r_ready, "a prepared start residual is for single-system solves");
+    if (any_x0 && !S[0].r_ready) {
         // start vector: r_hi = b_prec - M_prec x0 (systems without one have x0 = 0 and get b_prec)
         run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hx1, sys.d(), 0, st, hop_bytes(Hx1, SF64, L64, 0));
         run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hx2, sys.d(), 0, st, hop_bytes(Hx2, SF64, L64, 2));
@@ -1187,8 +1190,13 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
     // FP64 solution so that the next start vector is a combination of them in the internal layout
     EoSource src;
     prepare_source(g, "mm.", b, P.dagger, src, st);
-    std::vector<Field> X(n);
-    for (int i = 0; i < n; i++) X[i] = g->field("mm.X" + std::to_string(i), SF64, 2);
+    // and its final FP64 residual b_prec - M_prec x_e (for the next start residual)
+    std::vector<Field> X(n), R(n);
+    for (int i = 0; i < n; i++) {
+        X[i] = g->field("mm.X" + std::to_string(i), SF64, 2);
+        R[i] = g->field("mm.R" + std::to_string(i), SF64, 1);
+    }
+    std::vector<char> res_ok(n, 0);  // R[i] holds the residual of X[i] (a converged FP64 check)
     SysState* dummy = (SysState*)g->rawbuf("apply.sys", sizeof(SysState));
     std::vector<int> done;
     // solution-space minimisation: Gram entries <psi_i, psi_j> and <b, psi_i> of the solutions in
@@ -1206,6 +1214,7 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
         e.slot = 0;
         e.src = src;
         e.X64 = X[idx];
+        e.RH = R[idx];
         const int kall = (int)done.size();
         const int k = P.guess_order > 0 ? std::min(P.guess_order, kall) : kall;
         const int j_first = kall - k;  // the k most recently solved masses
@@ -1241,10 +1250,47 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
             } else {
                 c = minres_coefficients(Pg, qb, src.bb, kappas, done, j_first, k, kappas[idx]);
             }
-            // x0 = sum_j c_j x_j over the even half, in chunks (7 real or 4 complex inputs per sweep)
             const bool cplx = guess == WD_GUESS_MINRES;
+            bool fused = !cplx;
+            for (int jj = 0; jj < k; jj++)
+                if (c[jj].x != 0.0 && !res_ok[done[j_first + jj]]) fused = false;
+            // Lagrange guess: x0 and its start residual b_prec - M_prec x0 in one pass over the
+            // stored solutions and their FP64 residuals (k_guess; no operator application)
+            const double a = 1.0 / (2.0 * kappas[idx]);
+            double sum_c = 0.0, sum_ca = 0.0;
+            for (int jj = 0; jj < k && fused; jj++) {
+                sum_c += c[jj].x;
+                sum_ca += c[jj].x / (2.0 * kappas[done[j_first + jj]]);
+            }
+            for (int j0 = 0; j0 < k && fused; j0 += GUESS_MAX) {
+                GuessArgs A;
+                std::memset(&A, 0, sizeof(A));
+                A.x0 = X[idx].half(0);
+                A.r0 = R[idx].all();
+                A.n = R[idx].nsites();
+                A.acc = j0 > 0;
+                if (j0 == 0) {
+                    A.be = src.B64.half(0);
+                    A.h = src.HB.all();
+                    A.cb = a - sum_ca;
+                    A.ch = 1.0 - sum_c;
+                }
+                A.k = std::min(GUESS_MAX, k - j0);
+                for (int jj = 0; jj < A.k; jj++) {
+                    const int j = done[j_first + j0 + jj];
+                    const double aj = 1.0 / (2.0 * kappas[j]);
+                    A.xs[jj] = X[j].half(0);
+                    A.rs[jj] = R[j].all();
+                    A.c[jj] = c[j0 + jj].x;
+                    A.cx[jj] = c[j0 + jj].x * (aj * aj - a * a);
+                }
+                WD_CHECK_HIP(launch_guess(A, st));
+            }
+            if (fused) e.r_ready = true;
+            // otherwise x0 = sum_j c_j x_j over the even half, in chunks (7 real or 4 complex inputs
+            // per sweep), and the solver computes its residual with the FP64 operator
             const int per = cplx ? 4 : 7;
-            for (int j0 = 0; j0 < k; j0 += per) {
+            for (int j0 = 0; j0 < k && !fused; j0 += per) {
                 JobTable<SweepJob> L;
                 SweepJob sj = sweep_job(0, X[idx].stride);
                 sj.f[R_F0] = X[idx].half(0);
@@ -1278,6 +1324,7 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
             stats[idx].seconds = S[0].t1 - S[0].t0;
         }
         if (S[0].final_status != WD_OK && worst == WD_OK) worst = (wd_status)S[0].final_status;
+        res_ok[idx] = S[0].final_status == WD_OK && S[0].reliable > 0;
         done.push_back(idx);
         if (guess == WD_GUESS_MINRES && (int)done.size() < n) {
             // inner products of the new solution with b and with every stored solution (itself

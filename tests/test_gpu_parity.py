@@ -342,6 +342,26 @@ def test_bicgstab_m_parity(dims):
     g.close()
 
 
+def test_multimass_fp64_guess_iterations_match_oracle():
+    """FP64 even-odd sequential solves with the Lagrange guess: each mass's start residual comes
+    from the stored solutions and their FP64 residuals, not from the operator; the iteration
+    counts must equal the oracle driver's (which applies the operator) within one."""
+    dims = (8, 4, 4, 8)
+    U = li.random_links(dims, 1.0, 1011)
+    b = li.gaussian_field(dims, 2011)
+    kappas = [0.128, 0.120, 0.126, 0.122, 0.124]
+    g = wd.wd_gauge_create(_t(U))
+    for order in (0, 2):
+        xs, sts = wd.wd_multimass_solve(g, kappas, _t(b), guess=wd.WD_GUESS_POLY,
+                                        p=wd.params(tol=1e-10, mixed=False, guess_order=order))
+        _, its = oracle.multimass_sequential(U, kappas, b, tol=1e-10, guess="poly", eo=True, order=order)
+        _say("fp64 guess order", order, [s["iters"] for s in sts], "oracle", its)
+        for k, x, st, io in zip(kappas, xs, sts, its):
+            assert oracle.true_residual(U, k, _n(x), b) < 1e-10
+            assert abs(st["iters"] - io) <= 1
+    g.close()
+
+
 def test_multimass_sequential_poly_guess():
     dims = (8, 8, 8, 8)
     U = li.random_links(dims, 1.0, 1001)
