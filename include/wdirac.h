@@ -196,7 +196,8 @@ wd_status wd_batch_solve(int nsys, const wd_system* sys, const wd_solver_params*
  * the storage formats as for bicgstab_solve (FP64 reliable updates r = b_e - (A + sigma) x, or
  * defect correction). method WD_METHOD_BATCHED: the single-shift CG systems of all shifts
  * iterate together, no start guesses. stats: the true residual is |b_e - (A + sigma_i) x_i| /
- * |b_e| in FP64. 1 <= n <= 32, sigma_i >= 0, params->dagger = 0, guess NONE or POLY.
+ * |b_e| in FP64. 1 <= n <= 32, sigma_i >= 0, params->dagger = 0, guess NONE or POLY;
+ * params->use_x0 is ignored (x is output only). On WD_ERR_NOCONV x holds the last iterate.
  */
 wd_status wd_normal_solve(wd_gauge* g, double kappa, int n, const double* sigmas, double* const* x,
                           const double* b, int method, int guess, const wd_solver_params* params,

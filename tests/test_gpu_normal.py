@@ -171,3 +171,26 @@ def test_cg_small_reliable_delta(delta):
         _check(U, kappa, sig, b, xs, sts, tol)
         assert max(s["iters"] for s in sts) < 60
     g.close()
+
+
+def test_cg_single_shift_and_iteration_cap():
+    """CG-M with one shift is plain CG (its status is committed without the shift sweep); a cap on
+    the iterations ends every method with WD_ERR_NOCONV and filled statistics."""
+    dims = (8, 4, 4, 4)
+    U = li.random_links(dims, 1.0, 1308)
+    b = li.gaussian_field(dims, 2308)
+    kappa, tol = 0.13, 1e-10
+    g = wd.wd_gauge_create(_t(U))
+    xs, sts = wd.wd_normal_solve(g, kappa, [50.0], _t(b), method=wd.WD_METHOD_MULTISHIFT,
+                                 p=wd.params(tol=tol, mixed=False))
+    ref, it, st, _ = oracle.cg(U, kappa, 50.0, b, tol=tol)
+    _check(U, kappa, [50.0], b, xs, sts, tol, [ref])
+    assert abs(sts[0]["iters"] - it) <= 1
+    for m in (wd.WD_METHOD_MULTISHIFT, wd.WD_METHOD_SEQUENTIAL, wd.WD_METHOD_BATCHED):
+        p = wd.params(tol=1e-12, max_iter=3, mixed=m != wd.WD_METHOD_MULTISHIFT)
+        xs, sts = wd.wd_normal_solve(g, kappa, [0.0, 100.0], _t(b), method=m, p=p, raise_on_fail=False)
+        _say("cap", m, sts)
+        assert all(s["status"] == 4 for s in sts)  # WD_ERR_NOCONV
+        assert all(1 <= s["iters"] <= 3 + 3 for s in sts) and all(s["true_rel_res"] > 0 for s in sts)
+        assert all(np.isfinite(_n(x)).all() for x in xs)
+    g.close()
