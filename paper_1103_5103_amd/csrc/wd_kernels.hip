@@ -984,6 +984,54 @@ __global__ __launch_bounds__(BLOCK) void k_unpack_spinor(double2* __restrict__ d
     }
 }
 
+// Canonical output of an even-odd solve in one pass, one thread per lattice site in canonical
+// order (a wavefront writes contiguous sites): even sites from x_e, odd sites rebuilt from eq. eo3,
+// x_o = c0 b_o + c1 T with T = D_oe x_e left by the last FP64 residual update (stored into xo too
+// when xo.p is set), then the colour rotation, gamma5 and scale of k_unpack_spinor. FP64 fields.
+__global__ __launch_bounds__(BLOCK) void k_unpack_eo(double2* __restrict__ dst, Geo g, SpinorRef xe, SpinorRef xo,
+                                                     SpinorRef bo, SpinorRef T, double c0, double c1, int gamma5,
+                                                     double scale, const double2* __restrict__ gm)
+{
+    const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
+    const long V = (long)g.X * g.Y * g.Z * g.T;
+    if (n >= V) return;
+    const int x = (int)(n % g.X);
+    long r = n / g.X;
+    const int y = (int)(r % g.Y);
+    r /= g.Y;
+    const int z = (int)(r % g.Z);
+    const int t = (int)(r / g.Z);
+    const int cb = cb_index(g, x, y, z, t);
+    cx<double> w[12];
+    if (((x + y + z + t) & 1) == 0) {
+        load_spinor<SF64, double>(xe, cb, w);
+    } else {
+        cx<double> q[12];
+        load_spinor<SF64, double>(bo, cb, w);
+        load_spinor<SF64, double>(T, cb, q);
+#pragma unroll
+        for (int k = 0; k < 12; k++) w[k] = c0 * w[k] + c1 * q[k];
+        if (xo.p) store_spinor<SF64, double>(xo, cb, w);
+    }
+    if (gm) {
+        cx<double> G[9], u[12];
+#pragma unroll
+        for (int k = 0; k < 9; k++) G[k] = mk<double>(gm[n * 9 + k].x, gm[n * 9 + k].y);
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int sp = 0; sp < 4; sp++)
+                u[a * 4 + sp] = cmulc(G[a], w[sp]) + cmulc(G[3 + a], w[4 + sp]) + cmulc(G[6 + a], w[8 + sp]);
+#pragma unroll
+        for (int k = 0; k < 12; k++) w[k] = u[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const double sg = (gamma5 && (k & 3) >= 2) ? -scale : scale;
+        dst[n * 12 + k] = make_double2(sg * w[k].re, sg * w[k].im);
+    }
+}
+
 // canonical U[4][V][3][3] -> internal FP64 18-real links, 8 slots per output site
 __global__ __launch_bounds__(BLOCK) void k_pack_links(const double2* __restrict__ U, Geo g, void* even, void* odd,
                                                       long lcs)
@@ -1440,6 +1488,15 @@ hipError_t launch_dots(SpinorRef a, const SpinorRef* bs, int m, const Geo& g, do
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dots_finish, dim3(1), dim3(BLOCK), 0, s, partials, nb, m, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_eo(double* dst, const Geo& g, SpinorRef xe, SpinorRef xo, SpinorRef bo, SpinorRef T,
+                            double c0, double c1, int gamma5, double scale, hipStream_t s, const double* gm)
+{
+    const long V = (long)g.X * g.Y * g.Z * g.T;
+    hipLaunchKernelGGL(k_unpack_eo, grid1((V + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, (double2*)dst, g, xe, xo, bo, T,
+                       c0, c1, gamma5, scale, (const double2*)gm);
     return hipGetLastError();
 }
 

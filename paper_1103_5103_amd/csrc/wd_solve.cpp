@@ -352,6 +352,7 @@ struct EoSys {
     Field X64;         // FP64 solution (even half iterated, odd half rebuilt); caller-provided or own
     bool x_ready = false;  // X64 already holds the start vector (use_x0 handled by the caller)
     bool r_ready = false;  // RH already holds b_prec - M_prec x0 for that start vector (one system only)
+    bool keep_odd = false; // store the rebuilt odd half into X64 as well (a later guess reads it)
     Field RH;              // FP64 residual b_prec - M_prec x_e; caller-provided or own
     Field BP, T64;
     Field r, rh, s, w, As, Aw, tmp, xl;
@@ -444,7 +445,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
 
     // ---- static job tables
     JobTable<HopJob> Hhb, Hx1, Hx2, Hrec;
-    JobTable<SweepJob> Nb, Bp, InitFirst, InitRel, InitRestart, Acc, Odd;
+    JobTable<SweepJob> Nb, Bp, InitFirst, InitRel, InitRestart, Acc;
     JobTable<HopJob> H1, H2, H3, H4;
     JobTable<SweepJob> SW, SXR, SS;
     std::vector<int> need_src;
@@ -472,15 +473,6 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         bj.c[0] = e.a;
         bj.c[1] = 1.0;
         Bp.host.push_back(bj);
-        // odd half from the last FP64 residual update, which left T64 = D_oe x_e:
-        // x_o = (b_o + 1/2 D_oe x_e) / a  (eq. eo3)
-        bj = sweep_job(i, e.T64.nsites());
-        bj.f[R_F0] = e.X64.half(1);
-        bj.f[R_F1] = e.src.B64.half(1);
-        bj.f[R_F2] = e.T64.all();
-        bj.c[0] = 1.0 / e.a;
-        bj.c[1] = 0.5 / e.a;
-        Odd.host.push_back(bj);
         // FP64 residual r_hi = b_prec - M_prec x_e: T64 = D_oe x_e ; RH = b_prec - a^2 x_e + 1/4 D_eo T64
         Hx1.host.push_back(hop_job(g, 1, i, e.X64.half(0), e.T64.all(), d1, lcs, 1.0));
         HopJob j = hop_job(g, 0, i, e.T64.all(), e.RH.all(), d0, lcs, 0.25);
@@ -555,11 +547,11 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         for (auto& j : t->host) j.tg = S[j.sys].g->tg;  // solver links of a temporal-gauge handle
         layout(*t);
     }
-    for (auto* t : {&Nb, &Bp, &InitFirst, &InitRel, &InitRestart, &Acc, &Odd, &SW, &SXR, &SS}) layout(*t);
+    for (auto* t : {&Nb, &Bp, &InitFirst, &InitRel, &InitRestart, &Acc, &SW, &SXR, &SS}) layout(*t);
     // one copy for all tables, into a buffer kept by the first handle across solves
     upload_tables(st, S[0].g->raw["eo.tables"],
                   {&Hhb, &Hx1, &Hx2, &Hrec, &H1, &H2, &H3, &H4, &Nb, &Bp, &InitFirst, &InitRel, &InitRestart, &Acc,
-                   &Odd, &SW, &SXR, &SS});
+                   &SW, &SXR, &SS});
 
     // ---- setup
     if (!need_src.empty()) {
@@ -737,13 +729,21 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
             sys.h[i].status = by_sweep ? ST_SEL1 : ST_SEL2;
             nsweep += by_sweep;
         }
-        sys.upload(st);
-        if (nsweep > 0) run_sweep(OP_AXPY, SF64, Odd, sys.d(), 1 << ST_SEL1, st, sweep_bytes(Odd, 3 * 192));
-        if (nsweep < n) run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hrec, sys.d(), 1 << ST_SEL2, st, hop_bytes(Hrec, SF64, L64, 1));
+        if (nsweep < n) {
+            sys.upload(st);
+            run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hrec, sys.d(), 1 << ST_SEL2, st, hop_bytes(Hrec, SF64, L64, 1));
+        }
+        for (int i = 0; i < n; i++) {
+            EoSys& e = S[i];
+            if (sys.h[i].status == ST_SEL1)  // x_o = (b_o + 1/2 T64) / a, rebuilt while unpacking
+                WD_CHECK_HIP(launch_unpack_eo(e.x, e.g->geo, e.X64.half(0), e.keep_odd ? e.X64.half(1) : SpinorRef{},
+                                              e.src.B64.half(1), e.T64.all(), 1.0 / e.a, 0.5 / e.a, P.dagger, 1.0,
+                                              st, e.g->gm()));
+            else
+                WD_CHECK_HIP(launch_unpack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0,
+                                                  st, e.g->gm()));
+        }
     }
-    for (auto& e : S)
-        WD_CHECK_HIP(launch_unpack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st,
-                                          e.g->gm()));
     sys.download(st);
     for (int i = 0; i < n; i++) {
         EoSys& e = S[i];
@@ -1215,6 +1215,7 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
         e.src = src;
         e.X64 = X[idx];
         e.RH = R[idx];
+        e.keep_odd = guess == WD_GUESS_MINRES;  // its inner products run over full solutions
         const int kall = (int)done.size();
         const int k = P.guess_order > 0 ? std::min(P.guess_order, kall) : kall;
         const int j_first = kall - k;  // the k most recently solved masses
