@@ -45,6 +45,8 @@ constexpr int DOTS_MAX = 8;
 constexpr int GUESS_MAX = 8;
 struct GuessArgs {
     SpinorRef x0, r0, be, h;
+    SpinorRef bp;  // optional (first chunk): b_prec = a b_e + h
+    double a;
     SpinorRef xs[GUESS_MAX], rs[GUESS_MAX];
     double c[GUESS_MAX], cx[GUESS_MAX];
     double cb, ch;

@@ -353,6 +353,7 @@ struct EoSys {
     bool x_ready = false;  // X64 already holds the start vector (use_x0 handled by the caller)
     bool r_ready = false;  // RH already holds b_prec - M_prec x0 for that start vector (one system only)
     bool keep_odd = false; // store the rebuilt odd half into X64 as well (a later guess reads it)
+    bool bp_ready = false; // BP (caller-provided) already holds b_prec (one system only)
     Field RH;              // FP64 residual b_prec - M_prec x_e; caller-provided or own
     Field BP, T64;
     Field r, rh, s, w, As, Aw, tmp, xl;
@@ -412,7 +413,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         const std::string k = "eo" + std::to_string(e.slot) + ".";
         if (!e.src.B64.mem) prepare_source(e.g, k, e.b, P.dagger, e.src, st);
         if (!e.X64.mem) e.X64 = e.g->field(k + "X64", SF64, 2);
-        e.BP = e.g->field(k + "BP", SF64, 1);
+        if (!e.BP.mem) e.BP = e.g->field(k + "BP", SF64, 1);
         if (!e.RH.mem) e.RH = e.g->field(k + "RH", SF64, 1);
         e.T64 = e.g->field(k + "T64", SF64, 1);
         e.r = e.g->field(k + "r", SFL, 1);
@@ -573,8 +574,8 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         else
             WD_CHECK_HIP(hipMemsetAsync(e.X64.base(), 0, e.X64.mem->bytes, st));
     }
-    run_sweep(OP_AXPY, SF64, Bp, sys.d(), 0, st, sweep_bytes(Bp, 3 * 192));
-    WD_REQUIRE(n == 1 || !S[0].r_ready, "a prepared start residual is for single-system solves");
+    WD_REQUIRE(n == 1 || !(S[0].r_ready || S[0].bp_ready), "a prepared start is for single-system solves");
+    if (!S[0].bp_ready) run_sweep(OP_AXPY, SF64, Bp, sys.d(), 0, st, sweep_bytes(Bp, 3 * 192));
     if (any_x0 && !S[0].r_ready) {
         // start vector: r_hi = b_prec - M_prec x0 (systems without one have x0 = 0 and get b_prec)
         run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Hx1, sys.d(), 0, st, hop_bytes(Hx1, SF64, L64, 0));
@@ -1197,6 +1198,7 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
         R[i] = g->field("mm.R" + std::to_string(i), SF64, 1);
     }
     std::vector<char> res_ok(n, 0);  // R[i] holds the residual of X[i] (a converged FP64 check)
+    Field BPm = g->field("mm.BP", SF64, 1);
     SysState* dummy = (SysState*)g->rawbuf("apply.sys", sizeof(SysState));
     std::vector<int> done;
     // solution-space minimisation: Gram entries <psi_i, psi_j> and <b, psi_i> of the solutions in
@@ -1215,6 +1217,7 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
         e.src = src;
         e.X64 = X[idx];
         e.RH = R[idx];
+        e.BP = BPm;
         e.keep_odd = guess == WD_GUESS_MINRES;  // its inner products run over full solutions
         const int kall = (int)done.size();
         const int k = P.guess_order > 0 ? std::min(P.guess_order, kall) : kall;
@@ -1275,6 +1278,8 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
                     A.h = src.HB.all();
                     A.cb = a - sum_ca;
                     A.ch = 1.0 - sum_c;
+                    A.bp = BPm.all();  // b_prec of this mass, for its FP64 residual updates
+                    A.a = a;
                 }
                 A.k = std::min(GUESS_MAX, k - j0);
                 for (int jj = 0; jj < A.k; jj++) {
@@ -1287,7 +1292,7 @@ wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* cons
                 }
                 WD_CHECK_HIP(launch_guess(A, st));
             }
-            if (fused) e.r_ready = true;
+            if (fused) e.r_ready = e.bp_ready = true;
             // otherwise x0 = sum_j c_j x_j over the even half, in chunks (7 real or 4 complex inputs
             // per sweep), and the solver computes its residual with the FP64 operator
             const int per = cplx ? 4 : 7;
