@@ -812,7 +812,8 @@ __global__ __launch_bounds__(BLOCK) void k_sweep(const SweepJob* __restrict__ jo
 // of the mass),
 //   x0 = sum_j c_j x_j,
 //   r0 = b_prec(a) - M_prec(a) x0 = cb b_e + ch h + sum_j cx_j x_j + sum_j c_j r_j
-// (and b_prec(a) itself when bp.p is set)
+// (and b_prec(a) itself when bp.p is set). The shifted normal equations (A + s) x = b_e use the same
+// kernel without h: there r0 = (1 - sum c_j) b_e + sum_j c_j (s_j - s) x_j + sum_j c_j r_j.
 // with cb = a - sum c_j a_j, ch = 1 - sum c_j, cx_j = c_j (a_j^2 - a^2), since K x_j =
 // r_j - a_j b_e - h + a_j^2 x_j. FP64 half fields over n sites; acc = 1 adds to x0 and r0 (inputs
 // in chunks of GUESS_MAX).
@@ -831,7 +832,11 @@ __global__ __launch_bounds__(BLOCK) void k_guess(GuessArgs A)
     if (A.be.p) {
         cx<double> hv[12];
         load_spinor<SF64, double>(A.be, i, v);
-        load_spinor<SF64, double>(A.h, i, hv);
+        if (A.h.p) load_spinor<SF64, double>(A.h, i, hv);
+        else {
+#pragma unroll
+            for (int k = 0; k < 12; k++) hv[k] = mk<double>(0.0, 0.0);
+        }
 #pragma unroll
         for (int k = 0; k < 12; k++) r0[k] = r0[k] + A.cb * v[k] + A.ch * hv[k];
         if (A.bp.p) {

@@ -1369,6 +1369,7 @@ struct CgSys {
     double be2 = -1;       // |b_e|^2 (computed here when negative)
     Field X64;             // FP64 solution: even half iterated, odd half zero
     bool x_ready = false;  // the even half of X64 holds the start vector, the odd half is zero
+    bool r_ready = false;  // RH (caller-provided) holds b_e - (A + sigma) x0 (one system only)
     Field RH, T64, V64;    // FP64 residual (even) and operator temporaries (odd, even)
     Field r, p, t, v, w, xl;
     bool done = false;
@@ -1410,7 +1411,7 @@ static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream
         const std::string k = "cg" + std::to_string(e.slot) + ".";
         if (!e.src.B64.mem) prepare_source(e.g, k, e.b, 0, e.src, st);
         if (!e.X64.mem) e.X64 = e.g->field(k + "X64", SF64, 2);
-        e.RH = e.g->field(k + "RH", SF64, 1);
+        if (!e.RH.mem) e.RH = e.g->field(k + "RH", SF64, 1);
         e.T64 = e.g->field(k + "T64", SF64, 1);
         e.V64 = e.g->field(k + "V64", SF64, 1);
         e.r = e.g->field(k + "r", SFL, 1);
@@ -1566,7 +1567,8 @@ static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream
         if (!e.x_ready) WD_CHECK_HIP(hipMemsetAsync(e.X64.base(), 0, e.X64.mem->bytes, st));
         any_x0 = any_x0 || e.x_ready;
     }
-    if (any_x0) residual(0);
+    WD_REQUIRE(n == 1 || !S[0].r_ready, "a prepared start residual is for single-system solves");
+    if (any_x0 && !S[0].r_ready) residual(0);
     for (int i = 0; i < n; i++) {
         CgSys& e = S[i];
         sys.h[i].target2 = P.tol * P.tol * e.be2;
@@ -1997,8 +1999,13 @@ wd_status solve_normal(wd_gauge* g, double kappa, int n, const double* sigmas, d
     std::vector<int> order(n);
     for (int i = 0; i < n; i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return sigmas[p] > sigmas[q]; });
-    std::vector<Field> X(n);
-    for (int i = 0; i < n; i++) X[i] = g->field("nm.X" + std::to_string(i), SF64, 2);
+    // every shift keeps its FP64 solution and its final FP64 residual for the later start vectors
+    std::vector<Field> X(n), R(n);
+    for (int i = 0; i < n; i++) {
+        X[i] = g->field("nm.X" + std::to_string(i), SF64, 2);
+        R[i] = g->field("nm.R" + std::to_string(i), SF64, 1);
+    }
+    std::vector<char> res_ok(n, 0);
     SysState* dummy = (SysState*)g->rawbuf("apply.sys", sizeof(SysState));
     std::vector<int> done;
     double be2 = -1;
@@ -2006,6 +2013,7 @@ wd_status solve_normal(wd_gauge* g, double kappa, int n, const double* sigmas, d
         CgSys e = make(idx);
         e.slot = 0;
         e.X64 = X[idx];
+        e.RH = R[idx];
         e.be2 = be2;
         const int kall = (int)done.size();
         const int k = P.guess_order > 0 ? std::min(P.guess_order, kall) : kall;
@@ -2036,9 +2044,40 @@ wd_status solve_normal(wd_gauge* g, double kappa, int n, const double* sigmas, d
                     c[jj] = w;
                 }
             }
-            // x0 = sum_j c_j x_j over the even half (7 inputs per sweep), zero odd half
             WD_CHECK_HIP(hipMemsetAsync(X[idx].base(), 0, X[idx].mem->bytes, st));
-            for (int j0 = 0; j0 < k; j0 += 7) {
+            bool fused = true;
+            for (int jj = 0; jj < k; jj++)
+                if (c[jj] != 0.0 && !res_ok[done[j_first + jj]]) fused = false;
+            // x0 = sum_j c_j x_j and, since (A + s_j) x_j = b_e - r_j, its residual
+            // b_e - (A + s) x0 = (1 - sum c_j) b_e + sum_j c_j (s_j - s) x_j + sum_j c_j r_j in one
+            // pass over the stored solutions and residuals (k_guess; no operator application)
+            double sum_c = 0.0;
+            for (int jj = 0; jj < k; jj++) sum_c += c[jj];
+            for (int j0 = 0; j0 < k && fused; j0 += GUESS_MAX) {
+                GuessArgs A;
+                std::memset(&A, 0, sizeof(A));
+                A.x0 = X[idx].half(0);
+                A.r0 = R[idx].all();
+                A.n = R[idx].nsites();
+                A.acc = j0 > 0;
+                if (j0 == 0) {
+                    A.be = e.src.B64.half(0);
+                    A.cb = 1.0 - sum_c;
+                }
+                A.k = std::min(GUESS_MAX, k - j0);
+                for (int jj = 0; jj < A.k; jj++) {
+                    const int j = done[j_first + j0 + jj];
+                    A.xs[jj] = X[j].half(0);
+                    A.rs[jj] = R[j].all();
+                    A.c[jj] = c[j0 + jj];
+                    A.cx[jj] = c[j0 + jj] * (sigmas[j] - s);
+                }
+                WD_CHECK_HIP(launch_guess(A, st));
+            }
+            if (fused) e.r_ready = true;
+            // otherwise x0 = sum_j c_j x_j over the even half (7 inputs per sweep), and the solver
+            // computes its residual with the FP64 operator
+            for (int j0 = 0; j0 < k && !fused; j0 += 7) {
                 JobTable<SweepJob> L;
                 SweepJob sj = sweep_job(0, X[idx].stride);
                 sj.f[R_F0] = X[idx].half(0);
@@ -2059,6 +2098,7 @@ wd_status solve_normal(wd_gauge* g, double kappa, int n, const double* sigmas, d
         cg_solve(S, P, st, kPoll);
         be2 = S[0].be2;
         fill(idx, S[0], worst);
+        res_ok[idx] = S[0].final_status == WD_OK && S[0].reliable > 0;
         done.push_back(idx);
     }
     return worst;
