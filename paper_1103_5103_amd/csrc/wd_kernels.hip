@@ -3,10 +3,15 @@
 //  * k_hop     : the Wilson hopping term between parities (Sec. 2, eq. 3-4; the paper's dslash,
 //                Alg. 1) with the spin-projection trick of Table 1 and a fused epilogue
 //                out = c0 x0 + c1 x1 + c2 * hop, optionally followed by FP64 reductions and a
-//                finisher that updates the BiCGstab scalars.
+//                finisher that updates the solver scalars; the adjoint (DAG) variant serves the
+//                normal equations of CG / CG-M (Sec. 8).
 //  * k_sweep   : the fused BiCGstab vector updates of one iteration (Sec. 5: the x <- x - beta s +
-//                chi w update and its companions), plus the BiCGstab-M shift sweep (Sec. 6.1).
-//  * packing   : canonical complex128 layout <-> internal checkerboarded structure of arrays.
+//                chi w update and its companions), the BiCGstab-M shift sweep (Sec. 6.1), and the
+//                CG / CG-M updates.
+//  * k_finish  : fixed-order sums of the block partials and the scalar recurrences.
+//  * k_guess   : the sequential start vector (Sec. 6.2.1) and its residual without the operator.
+//  * packing   : canonical complex128 layout <-> internal checkerboarded structure of arrays;
+//                k_unpack_eo also rebuilds the odd half from eq. eo3.
 //  * k_grad    : link derivative of Re<eta, M^{-1} b> (outer products of projected spinors).
 #include "wd_kernels.hpp"
 
