@@ -176,6 +176,33 @@ def normal_equations(torch, wd, np, g, bd, kappa, W, reps):
     return out
 
 
+def links_8real(torch, wd, np, g, bd, kappas, W, reps, instrumented, gbs):
+    """The same sequential and batched mixed solves with the low-precision links in the 8-real
+    FP16 format (16 instead of 24 bytes per link; Sec. 4 names the further compression)."""
+    if W["links"] != "f16":
+        return None
+    p8 = wd.params(tol=1e-8, spinor=W["spinor"], links="f16", recon=8, delta=W["delta"])
+    x8 = [torch.zeros_like(bd) for _ in kappas]
+    t = {"sequential": [], "batched": []}
+    for rep in range(reps + 1):
+        for name, meth in (("sequential", wd.WD_METHOD_SEQUENTIAL), ("batched", wd.WD_METHOD_BATCHED)):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            _, sts = wd.wd_multimass_solve(g, kappas, bd, method=meth, xs=x8, p=p8)
+            torch.cuda.synchronize()
+            if rep > 0:
+                t[name].append(time.perf_counter() - a)
+            if name == "sequential":
+                st_seq = sts
+    rec = instrumented(lambda: wd.wd_multimass_solve(g, kappas, bd, method=wd.WD_METHOD_SEQUENTIAL, xs=x8, p=p8))
+    out = {f"solve_s_{k}": round(float(np.median(v)), 5) for k, v in t.items()}
+    out.update({"lo_hop_GBps": gbs(rec[0]), "lo_hop_avg_us": round(rec[0][0] / max(rec[0][1], 1) * 1e3, 2),
+                "lo_hop_bytes_per_launch": round(rec[0][2] / max(rec[0][1], 1)),
+                "iters": [s["iters"] for s in st_seq],
+                "true_rel_res": [float(f"{s['true_rel_res']:.3e}") for s in st_seq]})
+    return out
+
+
 def other_configs(torch, dev, wd, li, np, reps):
     """The batched and the differentiation workloads, timed beside the step.
 
@@ -365,6 +392,7 @@ def main():
 
     hop_ms, hop_n, hop_bytes = seq[0]
     normal = normal_equations(torch, wd, np, g, bd, kappas[-1], W, args.steps)
+    link8 = links_8real(torch, wd, np, g, bd, kappas, W, args.steps, instrumented, gbs)
     dev_bytes = g.device_bytes()
     g.close()
 
@@ -479,6 +507,7 @@ def main():
                                   "effective = the paper's no-reuse byte count"},
         "temporal_gauge": temporal,
         "normal_equations_cg": normal,
+        "links_8real": link8,
         "batched_96_systems": extra["batched"],
         "differentiation_16x32": extra["grad"],
         "device_bytes": dev_bytes,

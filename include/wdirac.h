@@ -72,7 +72,10 @@ typedef struct {
     wd_prec link_store;    /* storage of the links of the low-precision operator: WD_F32, WD_F16,
                               WD_BF16                                                                  */
     int recon;             /* link format of the low-precision operator: 12 (two rows stored, third
-                              rebuilt from unitarity) or 18                                            */
+                              rebuilt from unitarity), 18, or 8 (WD_F16 only: u01, u02, u10 and the
+                              phases of u00 and u20, the rest rebuilt from unitarity, 16 bytes per
+                              link; SU(3) links with |u00| < 1 - 1e-6 on every link, caller's gauge
+                              only, else WD_ERR_UNSUPPORTED)                                           */
     int eo;                /* 1: even-odd preconditioning (Sec. 6.2.3); single-mass solves only       */
     double delta_reliable; /* mixed: reliable update once |r| < delta * max|r| since the last one     */
     int use_x0;            /* 1: x holds the start vector on entry (single-mass solves only)          */

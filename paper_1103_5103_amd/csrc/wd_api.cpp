@@ -148,6 +148,14 @@ wd_status wd_gauge_create(wd_gauge** out, const wd_geom* geom, const double* U, 
                 for (double v : h) e = std::max(e, std::isfinite(v) ? v : 1.0);
             }
             g->recon_err = e;
+            double u = 0.0;
+            for (int p = 0; p < 2; p++) {
+                WD_CHECK_HIP(launch_recon_check(g->lk(L64_18, p), G.Vh, G.stride, (double*)bm.p, s, 1));
+                WD_CHECK_HIP(hipMemcpyAsync(h.data(), bm.p, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+                WD_CHECK_HIP(hipStreamSynchronize(s));
+                for (double v : h) u = std::max(u, std::isfinite(v) ? v : 1.0);
+            }
+            g->u00_max = u;
             const bool tg_on = hint && hint->temporal_gauge;
             if (e < 1e-12) {
                 if (tg_on) g->build_temporal_gauge(U, s);

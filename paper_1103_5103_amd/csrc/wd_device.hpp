@@ -17,7 +17,8 @@
 //   * links are stored per output parity and per output site: 8 matrices per site, slots 0..3
 //     the forward links U_mu(n), slots 4..7 the backward links already daggered,
 //     U_mu(n - mu)^dag, so every hop reads its 8 links fully coalesced. 12-real formats keep rows
-//     0 and 1 and rebuild row 2 = conj(row0 x row1), exact for SU(3).
+//     0 and 1 and rebuild row 2 = conj(row0 x row1), exact for SU(3); the 8-real FP16 format
+//     keeps 6 elements and 2 phases in one 16-byte chunk per link (recon8).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -29,21 +30,22 @@ constexpr int BLOCK_SITES = 256;
 
 // ---------------------------------------------------------------- formats
 enum SpinorFmt { SF64 = 0, SF32 = 1, SF16 = 2 };
-enum LinkFmt { L64_18 = 0, L64_12 = 1, L32_12 = 2, L16_12 = 3, LB16_12 = 4, L32_18 = 5, NLINKFMT = 6 };
+enum LinkFmt { L64_18 = 0, L64_12 = 1, L32_12 = 2, L16_12 = 3, LB16_12 = 4, L32_18 = 5, L16_8 = 6, NLINKFMT = 7 };
 
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 __host__ __device__ constexpr int spinor_chunks(int f) { return f == SF64 ? 12 : (f == SF32 ? 6 : 3); }
 __host__ __device__ constexpr int spinor_chunk_bytes(int f) { return 16; }
 __host__ __device__ constexpr int link_chunks(int f)
 {
-    return f == L64_18 ? 9 : f == L64_12 ? 6 : f == L32_18 ? 0 : 3;
+    return f == L64_18 ? 9 : f == L64_12 ? 6 : f == L32_18 ? 0 : f == L16_8 ? 1 : 3;
 }
 __host__ __device__ constexpr int link_chunk_bytes(int f)
 {
-    return (f == L64_18 || f == L64_12 || f == L32_12) ? 16 : 8;
+    return (f == L64_18 || f == L64_12 || f == L32_12 || f == L16_8) ? 16 : 8;
 }
 __host__ __device__ constexpr bool link_recon12(int f) { return f != L64_18 && f != L32_18; }
 // 16-byte chunks per site holding all 8 links of that site
@@ -317,6 +319,38 @@ __device__ __forceinline__ void recon_row2(cx<T> W[9])
     W[8] = cconj(W[0] * W[4] - W[1] * W[3]);
 }
 
+// 8-real FP16 links: one 16-byte chunk per link holding u01, u02, u10 and the phases of u00 and
+// u20 in units of pi. For U in SU(3) the rows are orthonormal and the inverse is the adjugate, so
+// |u00|^2 = 1 - |u01|^2 - |u02|^2, |u20|^2 = |u01|^2 + |u02|^2 - |u10|^2, and row 1 solves the
+// two linear conditions <row1, row0> = 0 and conj(u20) = u01 u12 - u02 u11, whose determinant is
+// N = |u01|^2 + |u02|^2; row 2 then follows as for the 12-real formats. The host refuses fields
+// with N near zero on some link (row 1 is not determined there).
+template <class T>
+__device__ __forceinline__ void recon8(const u16x8& q, cx<T> W[9])
+{
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) v[k] = (float)__builtin_bit_cast(_Float16, (unsigned short)q[k]);
+    const cx<float> a = {v[0], v[1]}, b = {v[2], v[3]}, c = {v[4], v[5]};
+    const float n = a.re * a.re + a.im * a.im + b.re * b.re + b.im * b.im;
+    const float m00 = __builtin_amdgcn_sqrtf(fmaxf(1.0f - n, 0.0f));
+    const float m20 = __builtin_amdgcn_sqrtf(fmaxf(n - c.re * c.re - c.im * c.im, 0.0f));
+    // the hardware sine and cosine take revolutions: angle / (2 pi) = (angle / pi) / 2
+    const float t0 = 0.5f * v[6], t2 = 0.5f * v[7];
+    const cx<float> u00 = {m00 * __builtin_amdgcn_cosf(t0), m00 * __builtin_amdgcn_sinf(t0)};
+    const cx<float> u20 = {m20 * __builtin_amdgcn_cosf(t2), m20 * __builtin_amdgcn_sinf(t2)};
+    const float inv = __builtin_amdgcn_rcpf(n);
+    const cx<float> r1 = -(c * cconj(u00)), r2 = cconj(u20);
+    const cx<float> u11 = inv * (r1 * a - cmulc(b, r2));
+    const cx<float> u12 = inv * (cmulc(a, r2) + b * r1);
+    W[0] = mk<T>((T)u00.re, (T)u00.im);
+    W[1] = mk<T>((T)a.re, (T)a.im);
+    W[2] = mk<T>((T)b.re, (T)b.im);
+    W[3] = mk<T>((T)c.re, (T)c.im);
+    W[4] = mk<T>((T)u11.re, (T)u11.im);
+    W[5] = mk<T>((T)u12.re, (T)u12.im);
+}
+
 template <int LF, class T>
 __device__ __forceinline__ void unpack16(unsigned short a, unsigned short b, cx<T>& z)
 {
@@ -357,6 +391,8 @@ __device__ __forceinline__ void load_link(const void* base, long lcs, int k, lon
             unpack16<LF, T>(q[0], q[1], W[2 * j]);
             unpack16<LF, T>(q[2], q[3], W[2 * j + 1]);
         }
+    } else if constexpr (LF == L16_8) {
+        recon8<T>(ld_stream<NT>((const u16x8*)base + chunk_at(NCT, lcs, i, k)), W);
     }
     if constexpr (link_recon12(LF)) recon_row2(W);
 }
@@ -366,7 +402,6 @@ template <int LF, class T, bool NT = true>
 __device__ __forceinline__ void load_link_pair(const void* base, long lcs, int mu, long i, cx<T> Wf[9], cx<T> Wb[9])
 {
     if constexpr (link_paired(LF)) {
-        typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
         const u16x8* p = (const u16x8*)base;
 #pragma unroll
         for (int j = 0; j < 3; j++) {
@@ -423,6 +458,17 @@ __device__ __forceinline__ void store_link(void* base, long lcs, int k, long i, 
             q[3] = f32_to_bf16((float)W[2 * j + 1].im);
             *pj = q;
         }
+    } else if constexpr (LF == L16_8) {
+        h8 q;
+        q[0] = (_Float16)(float)W[1].re;
+        q[1] = (_Float16)(float)W[1].im;
+        q[2] = (_Float16)(float)W[2].re;
+        q[3] = (_Float16)(float)W[2].im;
+        q[4] = (_Float16)(float)W[3].re;
+        q[5] = (_Float16)(float)W[3].im;
+        q[6] = (_Float16)(float)(atan2(W[0].im, W[0].re) * 0.31830988618379067154);
+        q[7] = (_Float16)(float)(atan2(W[6].im, W[6].re) * 0.31830988618379067154);
+        ((h8*)base)[chunk_at(NCT, lcs, i, k)] = q;
     }
 }
 

@@ -136,6 +136,7 @@ struct wd_gauge {
     std::map<std::string, std::shared_ptr<void>> graphs;  // captured iteration chunks by launch key
     hipStream_t stream = nullptr;
     double recon_err = 1.0;  // max |row2 - conj(row0 x row1)| over the links
+    double u00_max = 1.0;    // max |u00|^2 over the links (the 8-real format needs it below 1)
     // FP64 operator format of the solvers: 12-real when the links are SU(3) to rounding, else 18-real
     int f64_links() const { return recon_err < 1e-12 ? wd::L64_12 : wd::L64_18; }
     const void* lk(int lf, int parity) const;

@@ -1175,10 +1175,13 @@ __global__ __launch_bounds__(BLOCK) void k_transform_links(const double2* __rest
     }
 }
 
-// Largest deviation of row 2 from conj(row0 x row1) over all stored links (per block), which
-// decides whether the 12-real FP64 format reproduces the operator exactly.
+// Per-block maximum over all stored links of
+//   mode 0: the deviation of row 2 from conj(row0 x row1), which decides whether the 12-real
+//           FP64 format reproduces the operator exactly;
+//   mode 1: |u00|^2, which must stay below 1 for the 8-real format (row 1 is rebuilt by dividing
+//           by |u01|^2 + |u02|^2 = 1 - |u00|^2).
 __global__ __launch_bounds__(BLOCK) void k_recon_check(const void* __restrict__ lk, int Vh, long lcs,
-                                                       double* __restrict__ blockmax)
+                                                       double* __restrict__ blockmax, int mode)
 {
     __shared__ double lds[BLOCK / 64];
     const int cb = blockIdx.x * BLOCK + threadIdx.x;
@@ -1187,6 +1190,10 @@ __global__ __launch_bounds__(BLOCK) void k_recon_check(const void* __restrict__ 
         for (int k = 0; k < 8; k++) {
             cx<double> W[9];
             load_link<L64_18, double>(lk, lcs, k, cb, W);
+            if (mode == 1) {
+                m = fmax(m, W[0].re * W[0].re + W[0].im * W[0].im);
+                continue;
+            }
             cx<double> R[9];
             for (int j = 0; j < 6; j++) R[j] = W[j];
             recon_row2(R);
@@ -1202,10 +1209,10 @@ __global__ __launch_bounds__(BLOCK) void k_recon_check(const void* __restrict__ 
     }
 }
 
-hipError_t launch_recon_check(const void* lk, int Vh, long lcs, double* blockmax, hipStream_t s)
+hipError_t launch_recon_check(const void* lk, int Vh, long lcs, double* blockmax, hipStream_t s, int mode)
 {
     hipLaunchKernelGGL(k_recon_check, dim3((unsigned)((Vh + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, lk, Vh, lcs,
-                       blockmax);
+                       blockmax, mode);
     return hipGetLastError();
 }
 
@@ -1393,6 +1400,8 @@ hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* 
     HOP_REDS(SF16, L32_12, false)
     HOP_REDS(SF16, L16_12, false)
     HOP_REDS(SF16, LB16_12, false)
+    HOP_REDS(SF32, L16_8, false)
+    HOP_REDS(SF16, L16_8, false)
     HOP_DAG_64(L64_18)
     HOP_DAG_64(L64_12)
     HOP_DAG_LO(SF32, L32_12)
@@ -1401,6 +1410,8 @@ hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* 
     HOP_DAG_LO(SF16, L32_12)
     HOP_DAG_LO(SF16, L16_12)
     HOP_DAG_LO(SF16, LB16_12)
+    HOP_DAG_LO(SF32, L16_8)
+    HOP_DAG_LO(SF16, L16_8)
     return hipErrorInvalidValue;
 }
 
@@ -1466,6 +1477,7 @@ hipError_t launch_pack_links(const double* U, const Geo& g, void* even, void* od
     case L32_12: hipLaunchKernelGGL((k_convert_links<SRC_, L32_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break; \
     case L16_12: hipLaunchKernelGGL((k_convert_links<SRC_, L16_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break; \
     case LB16_12: hipLaunchKernelGGL((k_convert_links<SRC_, LB16_12>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break; \
+    case L16_8: hipLaunchKernelGGL((k_convert_links<SRC_, L16_8>), grid, dim3(BLOCK), 0, s, src, dst, Vh, lcs); break; \
     default: return hipErrorInvalidValue;                                                                          \
     }
 

@@ -36,7 +36,7 @@ hipError_t launch_unpack_eo(double* dst, const Geo& g, SpinorRef xe, SpinorRef x
 hipError_t launch_convert_links(int lf, int src_lf, const void* src, void* dst, int Vh, long lcs, hipStream_t s);
 // temporal gauge of canonical links U: gm = g(n) [V][3][3], Uf = transformed links [4][V][3][3]
 hipError_t launch_temporal_gauge(const double* U, const Geo& g, double* gm, double* Uf, hipStream_t s);
-hipError_t launch_recon_check(const void* lk, int Vh, long lcs, double* blockmax, hipStream_t s);
+hipError_t launch_recon_check(const void* lk, int Vh, long lcs, double* blockmax, hipStream_t s, int mode = 0);
 // out[2 j], out[2 j + 1] = <a, bs[j]> (j < m <= DOTS_MAX) over the real sites of full FP64 fields;
 // bs: device array of m views; partials: device, >= (2 stride / BLOCK + 1) * 2 * DOTS_MAX doubles
 constexpr int DOTS_MAX = 8;

@@ -46,7 +46,11 @@ int spinor_fmt_of(wd_prec p)
 
 int link_fmt_of(wd_prec p, int recon)
 {
-    if (recon != 12 && recon != 18) throw Error{WD_ERR_ARG, "recon must be 12 or 18"};
+    if (recon != 8 && recon != 12 && recon != 18) throw Error{WD_ERR_ARG, "recon must be 8, 12 or 18"};
+    if (recon == 8) {
+        if (p != WD_F16) throw Error{WD_ERR_UNSUPPORTED, "8-real links are stored in FP16 only"};
+        return L16_8;
+    }
     if (p == WD_F64) return recon == 12 ? L64_12 : L64_18;
     if (recon == 18) throw Error{WD_ERR_UNSUPPORTED, "18-real links are stored in FP64 only"};
     switch (p) {
@@ -324,6 +328,14 @@ static size_t link_bytes(int lf, long stride)
 void wd_gauge::ensure_links(int lf, hipStream_t s)
 {
     if (links[lf]) return;
+    if (lf == L16_8) {
+        if (recon_err > 1e-6)
+            throw Error{WD_ERR_UNSUPPORTED, "links are not SU(3): the 8-real format would change the operator"};
+        // row 1 is rebuilt by dividing by 1 - |u00|^2: refuse links (nearly) diagonal in row 0
+        if (u00_max > 1.0 - 1e-6)
+            throw Error{WD_ERR_UNSUPPORTED, "a link has |u00| = 1 to within 1e-6 (e.g. unit links): the 8-real "
+                                            "format cannot rebuild it; use recon 12"};
+    }
     auto m = std::make_unique<DevMem>(link_bytes(lf, geo.stride));
     const size_t half = m->bytes / 2;
     for (int p = 0; p < 2; p++)
@@ -337,6 +349,9 @@ void wd_gauge::ensure_slinks(int lf, hipStream_t s)
         ensure_links(lf, s);
         return;
     }
+    if (lf == L16_8)
+        throw Error{WD_ERR_UNSUPPORTED, "the temporal gauge makes time links unit matrices, which the 8-real "
+                                        "format cannot rebuild; use recon 12"};
     if (fixed[lf]) return;
     // every other format is converted from the transformed 12-real FP64 links (exact for SU(3))
     auto m = std::make_unique<DevMem>(link_bytes(lf, geo.stride));
