@@ -60,6 +60,27 @@ def test_mixed_solve_full_size_bench_config(big):
         assert abs(sts[i]["true_rel_res"] - res) < 1e-2 * res
 
 
+def test_mixed_solve_full_size_8real_links(big):
+    """The benchmark's sequential and batched mixed solves with 8-real FP16 links (recon = 8):
+    oracle residual of the lightest and heaviest masses; iteration counts within two per mass of
+    the 12-real links' (the rebuilt links are a small perturbation of the operator)."""
+    dims, U, b, g = big
+    kappas = [0.120 + 0.002 * k for k in range(8)]
+    p8 = wd.params(tol=1e-8, spinor="f32", links="f16", recon=8, delta=1e-3)
+    p12 = wd.params(tol=1e-8, spinor="f32", links="f16", delta=1e-3)
+    _, s12 = wd.wd_multimass_solve(g, kappas, _t(b), p=p12)
+    for method in (wd.WD_METHOD_SEQUENTIAL, wd.WD_METHOD_BATCHED):
+        xs, sts = wd.wd_multimass_solve(g, kappas, _t(b), method=method, p=p8)
+        for i in (0, 7):
+            res = oracle.true_residual(U, kappas[i], _n(xs[i]), b)
+            _say("32^3x64 8-real", method, kappas[i], sts[i], "oracle residual", res)
+            assert res < 1e-8
+            assert abs(sts[i]["true_rel_res"] - res) < 1e-2 * res
+        if method == wd.WD_METHOD_SEQUENTIAL:
+            assert all(a["iters"] <= c["iters"] + 2 for a, c in zip(sts, s12)), ([a["iters"] for a in sts],
+                                                                               [c["iters"] for c in s12])
+
+
 def test_multishift_full_size(big):
     dims, U, b, g = big
     kappas = [0.120 + 0.002 * k for k in range(8)]
