@@ -17,8 +17,10 @@ solve wall times and ms_per_step come from a first, uninstrumented pass over the
 pass runs each method on its own with the events on. The batched solve's hop reads the links once
 for all systems of a launch (they share the gauge field), so its compulsory bytes count the links
 once; it is reported separately. Beside the step, bench.py also times the paper's defect-correction
-scheme, the start-guess gain against its order, and the three methods on a handle that solves in
-temporal gauge. The CPU baseline is the plain FP64 oracle on the host cores.
+scheme, the start-guess gain against its order, the three methods on a handle that solves in
+temporal gauge, the normal equations (CG-M against single-shift CG), and the sequential and
+batched solves with other storage (8-real FP16 links; FP16 spinors). The CPU baseline is the
+plain FP64 oracle on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 32x64|16x32] [--no-cpu]
 """
@@ -176,30 +178,31 @@ def normal_equations(torch, wd, np, g, bd, kappa, W, reps):
     return out
 
 
-def links_8real(torch, wd, np, g, bd, kappas, W, reps, instrumented, gbs):
-    """The same sequential and batched mixed solves with the low-precision links in the 8-real
-    FP16 format (16 instead of 24 bytes per link; Sec. 4 names the further compression)."""
-    if W["links"] != "f16":
-        return None
-    p8 = wd.params(tol=1e-8, spinor=W["spinor"], links="f16", recon=8, delta=W["delta"])
-    x8 = [torch.zeros_like(bd) for _ in kappas]
+def storage_variant(torch, wd, np, g, bd, kappas, W, reps, instrumented, gbs, spinor, recon):
+    """The benchmark's sequential and batched mixed solves with another low-precision storage:
+    FP16 spinors (each site scaled by its largest component) or 8-real FP16 links (16 instead of
+    24 bytes per link; Sec. 4 names the further link compression)."""
+    p = wd.params(tol=1e-8, spinor=spinor, links="f16", recon=recon, delta=W["delta"])
+    xv = [torch.zeros_like(bd) for _ in kappas]
     t = {"sequential": [], "batched": []}
+    sts_of = {}
     for rep in range(reps + 1):
         for name, meth in (("sequential", wd.WD_METHOD_SEQUENTIAL), ("batched", wd.WD_METHOD_BATCHED)):
             torch.cuda.synchronize()
             a = time.perf_counter()
-            _, sts = wd.wd_multimass_solve(g, kappas, bd, method=meth, xs=x8, p=p8)
+            _, sts_of[name] = wd.wd_multimass_solve(g, kappas, bd, method=meth, xs=xv, p=p)
             torch.cuda.synchronize()
             if rep > 0:
                 t[name].append(time.perf_counter() - a)
-            if name == "sequential":
-                st_seq = sts
-    rec = instrumented(lambda: wd.wd_multimass_solve(g, kappas, bd, method=wd.WD_METHOD_SEQUENTIAL, xs=x8, p=p8))
-    out = {f"solve_s_{k}": round(float(np.median(v)), 5) for k, v in t.items()}
+    rec = instrumented(lambda: wd.wd_multimass_solve(g, kappas, bd, method=wd.WD_METHOD_SEQUENTIAL, xs=xv, p=p))
+    out = {"spinors": spinor, "links": f"f16, {recon}-real"}
+    out.update({f"solve_s_{k}": round(float(np.median(v)), 5) for k, v in t.items()})
     out.update({"lo_hop_GBps": gbs(rec[0]), "lo_hop_avg_us": round(rec[0][0] / max(rec[0][1], 1) * 1e3, 2),
                 "lo_hop_bytes_per_launch": round(rec[0][2] / max(rec[0][1], 1)),
-                "iters": [s["iters"] for s in st_seq],
-                "true_rel_res": [float(f"{s['true_rel_res']:.3e}") for s in st_seq]})
+                "iters_sequential": [s["iters"] for s in sts_of["sequential"]],
+                "iters_batched": [s["iters"] for s in sts_of["batched"]],
+                "true_rel_res_sequential": [float(f"{s['true_rel_res']:.3e}") for s in sts_of["sequential"]],
+                "max_true_rel_res_batched": float(f"{max(s['true_rel_res'] for s in sts_of['batched']):.3e}")})
     return out
 
 
@@ -392,7 +395,11 @@ def main():
 
     hop_ms, hop_n, hop_bytes = seq[0]
     normal = normal_equations(torch, wd, np, g, bd, kappas[-1], W, args.steps)
-    link8 = links_8real(torch, wd, np, g, bd, kappas, W, args.steps, instrumented, gbs)
+    link8 = spin16 = None
+    if W["links"] == "f16":
+        link8 = storage_variant(torch, wd, np, g, bd, kappas, W, args.steps, instrumented, gbs, W["spinor"], 8)
+    if W["spinor"] == "f32":
+        spin16 = storage_variant(torch, wd, np, g, bd, kappas, W, args.steps, instrumented, gbs, "f16", 12)
     dev_bytes = g.device_bytes()
     g.close()
 
@@ -508,6 +515,7 @@ def main():
         "temporal_gauge": temporal,
         "normal_equations_cg": normal,
         "links_8real": link8,
+        "spinors_f16": spin16,
         "batched_96_systems": extra["batched"],
         "differentiation_16x32": extra["grad"],
         "device_bytes": dev_bytes,
