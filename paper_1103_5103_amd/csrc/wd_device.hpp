@@ -181,6 +181,21 @@ __device__ __forceinline__ void load_spinor(const SpinorRef& r, long i, cx<T> v[
     }
 }
 
+// FP16 spinor without its per-site scale (returned): the hop applies the scale after the spin
+// projection and the link multiply, which are linear, folding it into its accumulation.
+template <class T>
+__device__ __forceinline__ float load_spinor16_raw(const SpinorRef& r, long i, cx<T> v[12])
+{
+    const float n = gld<float>(r.nrm, i);
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        h8 q = gld<h8>(r.p, chunk_at(3, r.cs, i, j));
+#pragma unroll
+        for (int k = 0; k < 4; k++) v[4 * j + k] = mk<T>((T)(float)q[2 * k], (T)(float)q[2 * k + 1]);
+    }
+    return n;
+}
+
 // NT: non-temporal stores (a hop's output is not read again within the launch)
 template <int SF, class T, bool NT = false>
 __device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const cx<T> v[12])
@@ -278,6 +293,18 @@ __device__ __forceinline__ void load_spinor_stg(const Stg<SF, true>& L, int k, c
             for (int m = 0; m < 4; m++) v[4 * j + m] = mk<T>((T)((float)q[2 * m] * n), (T)((float)q[2 * m + 1] * n));
         }
     }
+}
+
+template <class T>
+__device__ __forceinline__ float load_spinor16_stg_raw(const Stg<SF16, true>& L, int k, cx<T> v[12])
+{
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        const h8 q = L.c[j][k];
+#pragma unroll
+        for (int m = 0; m < 4; m++) v[4 * j + m] = mk<T>((T)(float)q[2 * m], (T)(float)q[2 * m + 1]);
+    }
+    return L.n[k];
 }
 
 // ---------------------------------------------------------------- streaming loads

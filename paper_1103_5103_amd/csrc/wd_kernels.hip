@@ -312,7 +312,16 @@ __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int 
     const int nb = cb_index(g, xx, yy, zz, tt) + dep;
 
     cx<T> psi[12];
-    if constexpr (STG && MU < 2) {
+    T sc = T(1);  // FP16 input: the site's scale, applied in the accumulation
+    if constexpr (SFI == SF16) {
+        if constexpr (STG && MU < 2) {
+            const int k = nb - in.base;
+            if ((unsigned)k < (unsigned)in.nsl) sc = (T)load_spinor16_stg_raw<T>(in.L, k, psi);
+            else sc = (T)load_spinor16_raw<T>(in.in, nb, psi);
+        } else {
+            sc = (T)load_spinor16_raw<T>(in.in, nb, psi);
+        }
+    } else if constexpr (STG && MU < 2) {
         const int k = nb - in.base;
         if ((unsigned)k < (unsigned)in.nsl) load_spinor_stg<SFI, T>(in.L, k, psi);
         else load_spinor<SFI, T>(in.in, nb, psi);
@@ -350,12 +359,24 @@ __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int 
             for (int a = 0; a < 3; a++) { g1[a] = -g1[a]; g2[a] = -g2[a]; }
         }
     }
+    if constexpr (SFI == SF16) {
+        // acc += sc * g as fused multiply-adds (mul_ik only swaps and negates components)
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-        acc[c * 4 + 3] = acc[c * 4 + 3] + g1[c];
-        acc[c * 4 + 2] = acc[c * 4 + 2] + g2[c];
-        acc[c * 4 + I1] = acc[c * 4 + I1] + mul_ik<E>(g1[c]);
-        acc[c * 4 + I2] = acc[c * 4 + I2] + mul_ik<F>(g2[c]);
+        for (int c = 0; c < 3; c++) {
+            const cx<T> e1 = mul_ik<E>(g1[c]), e2 = mul_ik<F>(g2[c]);
+            acc[c * 4 + 3] = {fmaf(sc, g1[c].re, acc[c * 4 + 3].re), fmaf(sc, g1[c].im, acc[c * 4 + 3].im)};
+            acc[c * 4 + 2] = {fmaf(sc, g2[c].re, acc[c * 4 + 2].re), fmaf(sc, g2[c].im, acc[c * 4 + 2].im)};
+            acc[c * 4 + I1] = {fmaf(sc, e1.re, acc[c * 4 + I1].re), fmaf(sc, e1.im, acc[c * 4 + I1].im)};
+            acc[c * 4 + I2] = {fmaf(sc, e2.re, acc[c * 4 + I2].re), fmaf(sc, e2.im, acc[c * 4 + I2].im)};
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            acc[c * 4 + 3] = acc[c * 4 + 3] + g1[c];
+            acc[c * 4 + 2] = acc[c * 4 + 2] + g2[c];
+            acc[c * 4 + I1] = acc[c * 4 + I1] + mul_ik<E>(g1[c]);
+            acc[c * 4 + I2] = acc[c * 4 + I2] + mul_ik<F>(g2[c]);
+        }
     }
 }
 
