@@ -81,6 +81,22 @@ def test_mixed_solve_full_size_8real_links(big):
                                                                                [c["iters"] for c in s12])
 
 
+def test_mixed_solve_full_size_fp16_spinors(big):
+    """The benchmark's sequential and batched mixed solves with FP16 spinors (per-site scale) and
+    FP16 12-real links: oracle residual of the lightest and heaviest masses."""
+    dims, U, b, g = big
+    kappas = [0.120 + 0.002 * k for k in range(8)]
+    p = wd.params(tol=1e-8, spinor="f16", links="f16", delta=1e-3)
+    for method in (wd.WD_METHOD_SEQUENTIAL, wd.WD_METHOD_BATCHED):
+        xs, sts = wd.wd_multimass_solve(g, kappas, _t(b), method=method, p=p)
+        for i in (0, 7):
+            res = oracle.true_residual(U, kappas[i], _n(xs[i]), b)
+            _say("32^3x64 FP16 spinors", method, kappas[i], sts[i], "oracle residual", res)
+            assert sts[i]["status"] == 0
+            assert res < 1e-8
+            assert abs(sts[i]["true_rel_res"] - res) < 1e-2 * res
+
+
 def test_multishift_full_size(big):
     dims, U, b, g = big
     kappas = [0.120 + 0.002 * k for k in range(8)]
