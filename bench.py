@@ -129,13 +129,13 @@ def practical_peak(torch, dev, n=1 << 27, reps=10):
     return 3 * 8 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
-def committed_traffic():
-    """Fabric bytes per low-precision hop launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel sources (else None)."""
+def committed_traffic(workload="32x64"):
+    """Fabric bytes per low-precision hop launch from the committed rocprofv3 counter summary of
+    this workload, if it was taken on the current kernel sources (else None)."""
     import hashlib
     import re
 
-    path = os.path.join(ROOT, "profiles", "hop_counters_32x64.md")
+    path = os.path.join(ROOT, "profiles", f"hop_counters_{workload}.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -467,7 +467,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(hop_gbs / HBM_PEAK_GBS, 4),
-            "traffic": committed_traffic(),
+            "traffic": committed_traffic(args.workload),
         },
         "vector_add_GBps": round(peak_va, 1),
         "frac_of_vector_add": round(hop_gbs / peak_va, 4),
