@@ -100,7 +100,9 @@ typedef struct {
     int iters;             /* Krylov iterations                                                    */
     int reliable_updates;  /* FP64 residual recomputations (mixed mode)                            */
     int status;            /* wd_status of this system                                             */
-    double true_rel_res;   /* |b - M x| / |b| recomputed in FP64 after the solve                   */
+    double true_rel_res;   /* |b - M x| / |b| in FP64 after the solve (even-odd solves: from their last
+                              FP64 even-site residual, which equals the full one up to the rounding
+                              of the rebuilt odd half; NaN after WD_ERR_NAN)                          */
     double seconds;        /* wall time of this system's solve (shared wall time for joint solves) */
 } wd_solver_stats;
 
@@ -217,6 +219,55 @@ wd_status wd_normal_solve(wd_gauge* g, double kappa, int n, const double* sigmas
  */
 wd_status wd_gauge_grad(wd_gauge* g, const double* x, const double* lam, double* dU, int project,
                         void* stream);
+
+/*
+ * How wd_apply_prec runs its two hops: each field selects one of the hop-kernel variants the
+ * solvers launch, so that every variant can be compared with the FP64 definition site by site.
+ */
+enum { WD_RED_NONE = 0, WD_RED_ZDOT = 1, WD_RED_OUTX = 2, WD_RED_NORM = 3 };
+typedef struct {
+    int red;          /* reduction fused into the second hop (the solvers' epilogues):
+                         WD_RED_NONE; WD_RED_ZDOT <in_e, out_e>; WD_RED_OUTX <out_e, in_e> and
+                         |out_e|^2; WD_RED_NORM |out_e|^2 (all sums in FP64)                      */
+    int stage;        /* LDS staging of the x and y neighbours: -1 library default, 0 off, 1 on   */
+    int nontemporal;  /* link loads and hop stores: -1 the solvers' policy, 0 ordinary, 1
+                         non-temporal                                                            */
+    int tile;         /* block order: -1 autotuned, 0 site order, tz > 0 t fastest within groups
+                         of tz z-planes (site order where the lattice does not allow tz)          */
+    int copies;       /* 1..64 systems in one launch; in and out then hold that many fields, one
+                         after the other. Systems on one gauge field share their link loads      */
+    int rhs_per_thread; /* -1: the tuned choice (as in the batched solvers); 0 or 1: one system
+                           per thread (systems sharing links run in interleaved block pairs);
+                           k in 2..4: the multi-RHS hop, up to k systems per thread with each
+                           link loaded once for all of them (FP32 / FP16 spinors, reductions
+                           other than WD_RED_NORM)                                               */
+    int dagger;       /* 1: the adjoint operator (both hops with swapped projectors, M^dag =
+                         gamma5 M gamma5); reductions WD_RED_NONE or WD_RED_ZDOT only            */
+} wd_op_variant;
+
+/* Defaults: red WD_RED_NONE, stage -1, nontemporal -1, tile -1, copies 1, rhs_per_thread -1,
+   dagger 0. */
+void wd_op_variant_default(wd_op_variant* v);
+
+/*
+ * The even-odd operator exactly as the solvers apply it in their storage formats (Sec. 6.2.3,
+ * eq. eo4, built from the hopping term of Sec. 2, eq. 3 and 4, with the spin projection of
+ * Table 1): `in` is packed into params->spinor_store (WD_F64 when params->mixed = 0) and the hops
+ * read the handle's links in params->link_store / params->recon (the FP64 operator's format when
+ * params->mixed = 0), in the handle's gauge (temporal gauge when the handle was created with it;
+ * sources and results are rotated as in the solvers). Two hops run:
+ *   out_o = D_oe in_e                                  (first hop, its stored low-precision value)
+ *   out_e = (1/(2 kappa))^2 in_e - 1/4 D_eo out_o     (second hop with the fused epilogue),
+ * so out_e = M_prec in_e and out_o is the hopping term from the even to the odd sites; with
+ * v->dagger the adjoint hops give out_o = (D_eo)^dag in_e and out_e = M_prec^dag in_e. The odd
+ * sites of `in` are ignored. in, out: device, v->copies consecutive [V][3][4] complex128 fields
+ * (distinct, not overlapping). dots (host, may be NULL): 3 doubles per copy, the fused sums of
+ * v->red in the order listed there (unused entries 0). v (may be NULL): defaults.
+ * Errors: WD_ERR_ARG, WD_ERR_UNSUPPORTED (format or variant not available for these links).
+ * Returns after the result is in `out` (synchronises the stream).
+ */
+wd_status wd_apply_prec(wd_gauge* g, double kappa, double* out, const double* in, const wd_solver_params* params,
+                        const wd_op_variant* v, double* dots, void* stream);
 
 /* Human-readable name of a status code (static string). */
 const char* wd_status_str(wd_status s);

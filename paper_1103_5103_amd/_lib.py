@@ -62,6 +62,22 @@ class SolverStats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class OpVariant(ctypes.Structure):
+    _fields_ = [
+        ("red", ctypes.c_int),
+        ("stage", ctypes.c_int),
+        ("nontemporal", ctypes.c_int),
+        ("tile", ctypes.c_int),
+        ("copies", ctypes.c_int),
+        ("rhs_per_thread", ctypes.c_int),
+        ("dagger", ctypes.c_int),
+    ]
+
+
+WD_RED_NONE, WD_RED_ZDOT, WD_RED_OUTX, WD_RED_NORM = range(4)
+RED = {"none": WD_RED_NONE, "zdot": WD_RED_ZDOT, "outx": WD_RED_OUTX, "norm": WD_RED_NORM}
+
+
 class System(ctypes.Structure):
     _fields_ = [("gauge", ctypes.c_void_p), ("kappa", ctypes.c_double), ("b", ctypes.c_void_p),
                 ("x", ctypes.c_void_p)]
@@ -71,7 +87,7 @@ EXPORTED = [
     "wd_params_default", "wd_gauge_create", "wd_gauge_destroy", "wd_apply", "wd_apply_dag", "bicgstab_solve",
     "bicgstab_m_solve", "wd_multimass_solve", "wd_batch_solve", "wd_normal_solve", "wd_gauge_grad",
     "wd_status_str", "wd_last_error", "wd_timing_enable", "wd_timing_reset", "wd_timing_get", "wd_gauge_device_bytes",
-    "wd_set_graphs",
+    "wd_set_graphs", "wd_op_variant_default", "wd_apply_prec",
 ]
 
 _lib = None
@@ -108,6 +124,10 @@ def load(path: str = LIBPATH):
     L.wd_normal_solve.argtypes = [vp, d, i, ctypes.POINTER(d), ctypes.POINTER(vp), vp, i, i,
                                   ctypes.POINTER(SolverParams), ctypes.POINTER(SolverStats), vp]
     L.wd_gauge_grad.argtypes = [vp, vp, vp, vp, i, vp]
+    L.wd_op_variant_default.argtypes = [ctypes.POINTER(OpVariant)]
+    L.wd_op_variant_default.restype = None
+    L.wd_apply_prec.argtypes = [vp, d, vp, vp, ctypes.POINTER(SolverParams), ctypes.POINTER(OpVariant),
+                                ctypes.POINTER(d), vp]
     L.wd_status_str.argtypes = [i]
     L.wd_status_str.restype = ctypes.c_char_p
     L.wd_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
@@ -122,7 +142,7 @@ def load(path: str = LIBPATH):
     L.wd_gauge_device_bytes.restype = ctypes.c_size_t
     for name in ("wd_gauge_create", "wd_gauge_destroy", "wd_apply", "wd_apply_dag", "bicgstab_solve",
                  "bicgstab_m_solve", "wd_multimass_solve", "wd_batch_solve", "wd_normal_solve", "wd_gauge_grad",
-                 "wd_last_error", "wd_timing_get"):
+                 "wd_last_error", "wd_timing_get", "wd_apply_prec"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -235,6 +255,37 @@ def wd_apply_dag(g: Gauge, kappa: float, psi: torch.Tensor, out: torch.Tensor | 
     _check(load().wd_apply_dag(g.handle, float(kappa), _ptr(out, "out", g.field_shape),
                                _ptr(psi, "in", g.field_shape), _stream()))
     return out
+
+
+def op_variant(red="none", stage=-1, nontemporal=-1, tile=-1, copies=1, rhs_per_thread=-1,
+               dagger=False) -> OpVariant:
+    v = OpVariant()
+    load().wd_op_variant_default(ctypes.byref(v))
+    v.red = RED[red] if isinstance(red, str) else int(red)
+    v.stage, v.nontemporal, v.tile = int(stage), int(nontemporal), int(tile)
+    v.copies, v.rhs_per_thread, v.dagger = int(copies), int(rhs_per_thread), int(bool(dagger))
+    return v
+
+
+def wd_apply_prec(g: Gauge, kappa: float, psi: torch.Tensor, p: SolverParams | None = None,
+                  v: OpVariant | None = None, out: torch.Tensor | None = None):
+    """The solvers' even-odd operator in their storage formats: returns (out, dots) with
+    out_e = M_prec in_e, out_o = D_oe in_e (adjoint hops with v.dagger). psi: one field
+    [T, Z, Y, X, 3, 4], or [copies, T, Z, Y, X, 3, 4] for v.copies systems in one launch.
+    dots: numpy array [copies, 3] of the fused sums of v.red."""
+    import numpy as np
+
+    p = params() if p is None else p
+    v = op_variant() if v is None else v
+    shape = tuple(psi.shape)
+    want = (v.copies, *g.field_shape) if v.copies > 1 or len(shape) == 7 else g.field_shape
+    out = torch.empty_like(psi) if out is None else out
+    _ptr(psi, "in", want)
+    _ptr(out, "out", want)
+    dots = (ctypes.c_double * (3 * v.copies))()
+    _check(load().wd_apply_prec(g.handle, float(kappa), _ptr(out, "out"), _ptr(psi, "in"), ctypes.byref(p),
+                                ctypes.byref(v), dots, _stream()))
+    return out, np.array(dots[:], dtype=np.float64).reshape(v.copies, 3)
 
 
 NONFATAL = (WD_OK, WD_ERR_NOCONV, WD_ERR_BREAKDOWN, WD_ERR_NAN)

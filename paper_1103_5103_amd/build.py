@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwdirac.so")
-SOURCES = ["wd_kernels.hip", "wd_runtime.cpp", "wd_solve.cpp", "wd_api.cpp"]
+SOURCES = ["wd_hop_lo.hip", "wd_mrhs.hip", "wd_hop64.hip", "wd_kernels.hip", "wd_runtime.cpp", "wd_solve.cpp", "wd_api.cpp"]
 ARCH = os.environ.get("WD_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -27,8 +27,7 @@ FLAGS = [
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    extra = os.environ.get("WD_DEFINES", "").split()  # e.g. -DWD_AOSOA=1 for layout experiments
-    cmd = ["hipcc", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -37,7 +36,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    workers = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", "4"))))
+    workers = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", "8"))))
     with cf.ThreadPoolExecutor(workers) as ex:
         objs = list(ex.map(_compile, SOURCES))
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]

@@ -18,6 +18,8 @@ wd_status solve_batch(int nsys, const wd_system* sys, const wd_solver_params& P,
                       hipStream_t st);
 wd_status solve_normal(wd_gauge* g, double kappa, int n, const double* sigmas, double* const* x, const double* b,
                        int method, int guess, const wd_solver_params& P, wd_solver_stats* stats, hipStream_t st);
+wd_status apply_prec(wd_gauge* g, double kappa, double* out, const double* in, const wd_solver_params& P,
+                     const wd_op_variant& v, double* dots, hipStream_t st);
 wd_status solve_multimass(wd_gauge* g, int n, const double* kappas, double* const* x, const double* b, int method,
                           int guess, const wd_solver_params& P, wd_solver_stats* stats, hipStream_t st);
 void set_graphs(bool on);
@@ -311,6 +313,38 @@ wd_status wd_batch_solve(int nsys, const wd_system* sys, const wd_solver_params*
         check_params(params);
         if (stats) std::memset(stats, 0, sizeof(*stats) * nsys);
         return solve_batch(nsys, sys, *params, stats, (hipStream_t)stream);
+    });
+}
+
+void wd_op_variant_default(wd_op_variant* v)
+{
+    if (!v) return;
+    std::memset(v, 0, sizeof(*v));
+    v->red = WD_RED_NONE;
+    v->stage = -1;
+    v->nontemporal = -1;
+    v->tile = -1;
+    v->copies = 1;
+    v->rhs_per_thread = -1;
+    v->dagger = 0;
+}
+
+wd_status wd_apply_prec(wd_gauge* g, double kappa, double* out, const double* in, const wd_solver_params* params,
+                        const wd_op_variant* v, double* dots, void* stream)
+{
+    return guarded([&]() -> wd_status {
+        if (!g) throw Error{WD_ERR_ARG, "NULL gauge"};
+        require_ptr(out, "out");
+        require_ptr(in, "in");
+        check_params(params);
+        wd_op_variant var;
+        wd_op_variant_default(&var);
+        if (v) var = *v;
+        if (var.copies < 1 || var.copies > 64) throw Error{WD_ERR_ARG, "copies must be in 1..64"};
+        const size_t bytes = (size_t)g->V * 24 * sizeof(double) * var.copies;
+        const char *o = (const char*)out, *i = (const char*)in;
+        if (o < i + bytes && i < o + bytes) throw Error{WD_ERR_ARG, "in and out overlap"};
+        return apply_prec(g, kappa, out, in, *params, var, dots, (hipStream_t)stream);
     });
 }
 

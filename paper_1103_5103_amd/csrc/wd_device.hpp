@@ -91,7 +91,7 @@ struct Geo {
 };
 
 // site coordinates of checkerboard index cb of parity p
-__device__ __forceinline__ void cb_coords(const Geo& g, int p, int cb, int& x, int& y, int& z, int& t)
+__host__ __device__ __forceinline__ void cb_coords(const Geo& g, int p, int cb, int& x, int& y, int& z, int& t)
 {
     unsigned u = (unsigned)cb;
     const unsigned xh = u % (unsigned)g.Xh;
@@ -102,26 +102,32 @@ __device__ __forceinline__ void cb_coords(const Geo& g, int p, int cb, int& x, i
     t = (int)(u / (unsigned)g.Z);
     x = 2 * (int)xh + ((p + y + z + t) & 1);
 }
-__device__ __forceinline__ int cb_index(const Geo& g, int x, int y, int z, int t)
+__host__ __device__ __forceinline__ int cb_index(const Geo& g, int x, int y, int z, int t)
 {
     return (x >> 1) + g.Xh * (y + g.Y * (z + g.Z * t));
 }
+// checkerboard index of the neighbour of (x, y, z, t) in direction MU, forward (D = 0) or backward
+// (D = 1), with periodic wrap (the time boundary sign is applied by the hop, not here)
+template <int MU, int D>
+__host__ __device__ __forceinline__ int nb_index(const Geo& g, int x, int y, int z, int t)
+{
+    if constexpr (MU == 0) x = D == 0 ? (x + 1 == g.X ? 0 : x + 1) : (x == 0 ? g.X - 1 : x - 1);
+    if constexpr (MU == 1) y = D == 0 ? (y + 1 == g.Y ? 0 : y + 1) : (y == 0 ? g.Y - 1 : y - 1);
+    if constexpr (MU == 2) z = D == 0 ? (z + 1 == g.Z ? 0 : z + 1) : (z == 0 ? g.Z - 1 : z - 1);
+    if constexpr (MU == 3) t = D == 0 ? (t + 1 == g.T ? 0 : t + 1) : (t == 0 ? g.T - 1 : t - 1);
+    return cb_index(g, x, y, z, t);
+}
 
 // ---------------------------------------------------------------- chunk addressing
-// WD_AOSOA = B > 0 stores fields and links in blocks of B sites with all chunks of a block
-// contiguous (chunk j of site i at ((i / B) * nchunks + j) * B + i % B), so one wavefront's loads
-// of a site quantity fall into one contiguous region and a kernel keeps a few DRAM streams open
-// instead of one per chunk (measured on MI355X: hops +6%, sweeps +10% over B = 0).
-// WD_AOSOA = 0 keeps one array per chunk (chunk j of site i at j * cs + i).
-#ifndef WD_AOSOA
-#define WD_AOSOA 64
-#endif
-constexpr long AOSOA_B = WD_AOSOA;  // sites per block (a power of two dividing 256), 0: plain arrays
-constexpr bool AOSOA = AOSOA_B > 0;
+// Fields and links are stored in blocks of AOSOA_B sites with all chunks of a block contiguous
+// (chunk j of site i at ((i / B) * nchunks + j) * B + i % B), so one wavefront's loads of a site
+// quantity fall into one contiguous region and a kernel keeps a few DRAM streams open instead of
+// one per chunk (measured on MI355X: hops +6%, sweeps +10% over one array per chunk).
+constexpr long AOSOA_B = 64;  // sites per block (a power of two dividing 256)
+constexpr bool AOSOA = true;
 __host__ __device__ __forceinline__ long chunk_at(int nchunks, long cs, long i, int j)
 {
-    if constexpr (AOSOA) return ((i / AOSOA_B) * nchunks + j) * AOSOA_B + (i % AOSOA_B);
-    else return j * cs + i;
+    return ((i / AOSOA_B) * nchunks + j) * AOSOA_B + (i % AOSOA_B);
 }
 
 // ---------------------------------------------------------------- global-memory accessors
@@ -196,6 +202,15 @@ __device__ __forceinline__ float load_spinor16_raw(const SpinorRef& r, long i, c
     return n;
 }
 
+// FP16 spinor storage divides a site's 24 values by their largest magnitude m. A site with m below
+// the smallest normal float (where 1/m would overflow to infinity and 0 * inf give NaN) is stored
+// as zero; so is m = 0. An infinite or NaN m keeps its scale (inv = 0): the load then yields NaN,
+// which the solver reports.
+__host__ __device__ __forceinline__ float f16_site_inv(float m)
+{
+    return m >= 1.17549435e-38f && m <= 3.40282347e+38f ? 1.0f / m : 0.0f;
+}
+
 // NT: non-temporal stores (a hop's output is not read again within the launch)
 template <int SF, class T, bool NT = false>
 __device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const cx<T> v[12])
@@ -213,8 +228,8 @@ __device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const c
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; k++) m = fmaxf(m, fmaxf(fabsf((float)v[k].re), fabsf((float)v[k].im)));
-        const float inv = m > 0.f ? 1.0f / m : 0.f;
-        gst<float, NT>(r.nrm, i, m);
+        const float inv = f16_site_inv(m);
+        gst<float, NT>(r.nrm, i, inv == 0.f && m < 1.0f ? 0.f : m);
 #pragma unroll
         for (int j = 0; j < 3; j++) {
             h8 q;
@@ -311,14 +326,11 @@ __device__ __forceinline__ float load_spinor16_stg_raw(const Stg<SF16, true>& L,
 // A hop of one system reads each link exactly once: non-temporal loads keep the links from
 // evicting the neighbour spinors that other sites of the same XCD are about to re-read from L2.
 // When several systems share the links (interleaved groups) ordinary loads let them hit in L2.
-#ifndef WD_NT_LINKS
-#define WD_NT_LINKS 1
-#endif
 template <bool NT = true, class V>
 __device__ __forceinline__ V ld_stream(const V* p)
 {
     typedef __attribute__((address_space(1))) const V GV;
-    if constexpr (WD_NT_LINKS && NT) return __builtin_nontemporal_load((GV*)p);
+    if constexpr (NT) return __builtin_nontemporal_load((GV*)p);
     else return *(GV*)p;
 }
 

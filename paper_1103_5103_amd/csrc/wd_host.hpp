@@ -157,8 +157,10 @@ void* pinned(size_t bytes);
 char* stage_alloc(size_t bytes);
 
 // launch helpers with optional timing
+// stage / ntl: -1 the defaults (LDS staging as built; non-temporal link loads unless the launch's
+// links are shared or small), else forced (0 off, 1 on)
 void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>& t, SysState* sys, int gated,
-             hipStream_t s, double bytes_per_site_total);
+             hipStream_t s, double bytes_per_site_total, int stage = -1, int ntl = -1);
 void run_sweep(int op, int sfl, const JobTable<SweepJob>& t, SysState* sys, int gated, hipStream_t s,
                double bytes_total);
 

@@ -13,67 +13,16 @@
 //  * packing   : canonical complex128 layout <-> internal checkerboarded structure of arrays;
 //                k_unpack_eo also rebuilds the odd half from eq. eo3.
 //  * k_grad    : link derivative of Re<eta, M^{-1} b> (outer products of projected spinors).
-#include "wd_kernels.hpp"
+#include "wd_hop.hpp"
 
 #include <cstdlib>
 
-// Occupancy hints of the hop kernel (minimum waves per SIMD; 0 lets the compiler choose) and
-// the XCD-aware block order, selectable at build time.
-#ifndef WD_HOP_WAVES_LO
-#define WD_HOP_WAVES_LO 0
-#endif
-#ifndef WD_HOP_WAVES_64
-#define WD_HOP_WAVES_64 0
-#endif
-#ifndef WD_XCD_REMAP
-#define WD_XCD_REMAP 1
-#endif
-// Directions whose loads may be scheduled together in the hop (8: all, 1: one at a time). A
-// scheduling barrier between groups bounds the live registers instead of spilling.
-#ifndef WD_HOP_GROUP_LO
-#define WD_HOP_GROUP_LO 2
-#endif
-#ifndef WD_HOP_GROUP_64
-#define WD_HOP_GROUP_64 2
-#endif
-
 namespace wd {
 
-#ifndef WD_HOP_STAGE
-#define WD_HOP_STAGE 1
-#endif
-// LDS staging of the x and y neighbours in the low-precision hop: build default WD_HOP_STAGE,
-// overridden by the environment variable of the same name (0 or 1) for comparisons.
-int hop_stage_default()
-{
-    static const int v = [] {
-        const char* e = std::getenv("WD_HOP_STAGE");
-        return e ? (std::atoi(e) != 0) : WD_HOP_STAGE;
-    }();
-    return v;
-}
-
-#ifndef WD_HOP_STAGE64
-#define WD_HOP_STAGE64 1
-#endif
-// the same for the FP64 hop (61 KB of LDS per block); environment variable WD_HOP_STAGE64
-int hop_stage64_default()
-{
-    static const int v = [] {
-        const char* e = std::getenv("WD_HOP_STAGE64");
-        return e ? (std::atoi(e) != 0) : WD_HOP_STAGE64;
-    }();
-    return v;
-}
-
-// MI355X has 8 XCDs, each with its own L2; consecutive workgroups go to consecutive XCDs. This
-// bijection on [0, nb) hands each XCD one contiguous eighth of the blocks, so the neighbour
-// sites a block gathers were mostly loaded by blocks of the same XCD and hit in its L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb)
-{
-    const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
-}
+// LDS staging of the x and y neighbours in the hop (both the low-precision and the FP64 hop; a
+// launch may turn it off, which changes no arithmetic)
+int hop_stage_default() { return 1; }
+int hop_stage64_default() { return 1; }
 
 // ================================================================ finishers
 
@@ -228,18 +177,6 @@ __device__ void finish(SysState* S, const double* tot)
     }
 }
 
-// Block reduction of NR partial sums; thread 0 stores the block's partial at slot rb.
-template <int NR>
-__device__ __forceinline__ void write_partials(double v[NRED], SysState* S, int rb)
-{
-    __shared__ double lds[NRED * (BLOCK / 64)];
-    block_sum<NR>(v, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NR; k++) S->partials[(long)rb * NRED + k] = v[k];
-    }
-}
-
 // One block per system: fixed-order sum of the partials of the preceding kernel, then the
 // finisher. Gated launches skip systems that were not RUNNING (the preceding kernel skipped
 // them too, since only finishers change the status).
@@ -260,283 +197,6 @@ __global__ __launch_bounds__(BLOCK) void k_finish(const FinJob* __restrict__ fin
         block_sum<NR>(tot, lds);
     }
     if (threadIdx.x == 0) finish<FIN>(S, tot);
-}
-
-// job of block b: jobs are sorted by blk0
-template <class J>
-__device__ __forceinline__ int find_job(const J* jobs, int njobs, int b)
-{
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].blk0 <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-// ================================================================ hop
-
-// Projection data of Table 1: with the hop's spin matrix written P = v1 v1^dag + v2 v2^dag,
-// v1^dag has a 1 in spin slot 3 and the unit e = i^E in slot I1, v2^dag has a 1 in slot 2 and
-// f = i^F in slot I2. For 1 - gamma_mu (forward hop of M):
-//   mu = x: e = i,  f = i   (I1 = 0, I2 = 1)      mu = y: e = -1, f = 1  (I1 = 0, I2 = 1)
-//   mu = z: e = -i, f = i   (I1 = 1, I2 = 0)      mu = t: e = 1,  f = 1  (I1 = 1, I2 = 0)
-// and 1 + gamma_mu negates e and f. Shrink: h1 = psi_3 + conj(e) psi_I1, h2 = psi_2 + conj(f) psi_I2;
-// expand: col3 += g1, col I1 += e g1, col2 += g2, col I2 += f g2 with g = U h (colour multiply).
-template <int MU> struct Proj;
-template <> struct Proj<0> { static constexpr int E = 1, F = 1, I1 = 0, I2 = 1; };
-template <> struct Proj<1> { static constexpr int E = 2, F = 0, I1 = 0, I2 = 1; };
-template <> struct Proj<2> { static constexpr int E = 3, F = 1, I1 = 1, I2 = 0; };
-template <> struct Proj<3> { static constexpr int E = 0, F = 0, I1 = 1, I2 = 0; };
-
-// Where a hop reads its input sites: memory, or (STG) an LDS copy of the window [base, base + nsl)
-// of input sites for the x and y directions.
-template <int SF, bool STG>
-struct HopIn {
-    const SpinorRef& in;
-    const Stg<SF, STG>& L;
-    int base, nsl;
-    bool tg;  // temporal gauge: unit time links inside the lattice
-};
-
-template <int MU, int D, bool DAG, int SFI, bool STG, class T>
-__device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int z, int t, const HopIn<SFI, STG>& in,
-                                        const cx<T> W[9], cx<T> acc[12], int dep, bool unit)
-{
-    int xx = x, yy = y, zz = z, tt = t;
-    if constexpr (MU == 0) xx = D == 0 ? (x + 1 == g.X ? 0 : x + 1) : (x == 0 ? g.X - 1 : x - 1);
-    if constexpr (MU == 1) yy = D == 0 ? (y + 1 == g.Y ? 0 : y + 1) : (y == 0 ? g.Y - 1 : y - 1);
-    if constexpr (MU == 2) zz = D == 0 ? (z + 1 == g.Z ? 0 : z + 1) : (z == 0 ? g.Z - 1 : z - 1);
-    if constexpr (MU == 3) tt = D == 0 ? (t + 1 == g.T ? 0 : t + 1) : (t == 0 ? g.T - 1 : t - 1);
-    const int nb = cb_index(g, xx, yy, zz, tt) + dep;
-
-    cx<T> psi[12];
-    T sc = T(1);  // FP16 input: the site's scale, applied in the accumulation
-    if constexpr (SFI == SF16) {
-        if constexpr (STG && MU < 2) {
-            const int k = nb - in.base;
-            if ((unsigned)k < (unsigned)in.nsl) sc = (T)load_spinor16_stg_raw<T>(in.L, k, psi);
-            else sc = (T)load_spinor16_raw<T>(in.in, nb, psi);
-        } else {
-            sc = (T)load_spinor16_raw<T>(in.in, nb, psi);
-        }
-    } else if constexpr (STG && MU < 2) {
-        const int k = nb - in.base;
-        if ((unsigned)k < (unsigned)in.nsl) load_spinor_stg<SFI, T>(in.L, k, psi);
-        else load_spinor<SFI, T>(in.in, nb, psi);
-    } else {
-        load_spinor<SFI, T>(in.in, nb, psi);
-    }
-    constexpr bool minus = (D == 0) != DAG;  // projector 1 - gamma
-    constexpr int E = Proj<MU>::E + (minus ? 0 : 2);
-    constexpr int F = Proj<MU>::F + (minus ? 0 : 2);
-    constexpr int I1 = Proj<MU>::I1, I2 = Proj<MU>::I2;
-    cx<T> h1[3], h2[3];
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        h1[c] = psi[c * 4 + 3] + mul_ik<-E>(psi[c * 4 + I1]);
-        h2[c] = psi[c * 4 + 2] + mul_ik<-F>(psi[c * 4 + I2]);
-    }
-    cx<T> g1[3], g2[3];
-    if (unit) {
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            g1[a] = h1[a];
-            g2[a] = h2[a];
-        }
-    } else {
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            g1[a] = W[a * 3] * h1[0] + W[a * 3 + 1] * h1[1] + W[a * 3 + 2] * h1[2];
-            g2[a] = W[a * 3] * h2[0] + W[a * 3 + 1] * h2[1] + W[a * 3 + 2] * h2[2];
-        }
-    }
-    if constexpr (MU == 3) {
-        const bool flip = g.anti && (D == 0 ? (t == g.T - 1) : (t == 0));
-        if (flip) {
-#pragma unroll
-            for (int a = 0; a < 3; a++) { g1[a] = -g1[a]; g2[a] = -g2[a]; }
-        }
-    }
-    if constexpr (SFI == SF16) {
-        // acc += sc * g as fused multiply-adds (mul_ik only swaps and negates components)
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            const cx<T> e1 = mul_ik<E>(g1[c]), e2 = mul_ik<F>(g2[c]);
-            acc[c * 4 + 3] = {fmaf(sc, g1[c].re, acc[c * 4 + 3].re), fmaf(sc, g1[c].im, acc[c * 4 + 3].im)};
-            acc[c * 4 + 2] = {fmaf(sc, g2[c].re, acc[c * 4 + 2].re), fmaf(sc, g2[c].im, acc[c * 4 + 2].im)};
-            acc[c * 4 + I1] = {fmaf(sc, e1.re, acc[c * 4 + I1].re), fmaf(sc, e1.im, acc[c * 4 + I1].im)};
-            acc[c * 4 + I2] = {fmaf(sc, e2.re, acc[c * 4 + I2].re), fmaf(sc, e2.im, acc[c * 4 + I2].im)};
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            acc[c * 4 + 3] = acc[c * 4 + 3] + g1[c];
-            acc[c * 4 + 2] = acc[c * 4 + 2] + g2[c];
-            acc[c * 4 + I1] = acc[c * 4 + I1] + mul_ik<E>(g1[c]);
-            acc[c * 4 + I2] = acc[c * 4 + I2] + mul_ik<F>(g2[c]);
-        }
-    }
-}
-
-template <int SF> struct HopGroup { static constexpr int G = WD_HOP_GROUP_LO; };
-template <> struct HopGroup<SF64> { static constexpr int G = WD_HOP_GROUP_64; };
-
-// Between groups of directions: an empty asm that reads every accumulator and then "writes"
-// the zero offset used by the next group's addresses. The volatile asms keep their order, so
-// the next group's loads cannot be issued before this group's results exist, which bounds the
-// number of live load registers (the FP64 hop otherwise spills).
-template <class T>
-__device__ __forceinline__ void order_after(cx<T> acc[12], int& dep)
-{
-#pragma unroll
-    for (int k = 0; k < 12; k += 3)
-        asm volatile("" ::"v"(acc[k].re), "v"(acc[k].im), "v"(acc[k + 1].re), "v"(acc[k + 1].im), "v"(acc[k + 2].re),
-                     "v"(acc[k + 2].im));
-    asm volatile("" : "+v"(dep));
-}
-
-template <int D, int G, class T>
-__device__ __forceinline__ void group_barrier(cx<T> acc[12], int& dep)
-{
-    // after direction D (0..7): close the group
-    if constexpr (G < 8 && ((D + 1) % G) == 0 && D < 7) order_after(acc, dep);
-}
-
-// Both directions of axis MU; the two links are loaded together (one 16-byte load per chunk for
-// the paired 16-bit formats). G = directions per ordering group. NTL: non-temporal link loads.
-template <int MU, int G, bool DAG, int SFI, int LF, bool STG, bool NTL, class T>
-__device__ __forceinline__ void hop_axis(const Geo& g, int cb, int x, int y, int z, int t, const HopIn<SFI, STG>& in,
-                                         const void* links, long lcs, cx<T> acc[12], int& dep)
-{
-    cx<T> Wf[9], Wb[9];
-    // temporal gauge: U_t(n) is the unit matrix unless t = T - 1, U_t(n - t)^dag unless t = 0
-    const bool unit_f = MU == 3 && in.tg && t != g.T - 1;
-    const bool unit_b = MU == 3 && in.tg && t != 0;
-    if (!(unit_f && unit_b)) {
-        load_link_pair<LF, T, NTL>(links, lcs, MU, cb + dep, Wf, Wb);
-    }
-    hop_dir<MU, 0, DAG, SFI, STG, T>(g, cb, x, y, z, t, in, Wf, acc, dep, unit_f);
-    group_barrier<2 * MU, G>(acc, dep);
-    hop_dir<MU, 1, DAG, SFI, STG, T>(g, cb, x, y, z, t, in, Wb, acc, dep, unit_b);
-    group_barrier<2 * MU + 1, G>(acc, dep);
-}
-
-template <bool DAG, int SFI, int LF, bool STG, bool NTL, class T>
-__device__ __forceinline__ void hop_site(const Geo& g, int p, int cb, const HopIn<SFI, STG>& in, const void* links,
-                                         long lcs, cx<T> acc[12])
-{
-    constexpr int G = HopGroup<SFI>::G;
-    int x, y, z, t;
-    cb_coords(g, p, cb, x, y, z, t);
-#pragma unroll
-    for (int k = 0; k < 12; k++) acc[k] = mk<T>(T(0), T(0));
-    int dep = 0;
-    hop_axis<0, G, DAG, SFI, LF, STG, NTL, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    hop_axis<1, G, DAG, SFI, LF, STG, NTL, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    hop_axis<2, G, DAG, SFI, LF, STG, NTL, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-    hop_axis<3, G, DAG, SFI, LF, STG, NTL, T>(g, cb, x, y, z, t, in, links, lcs, acc, dep);
-}
-
-template <int SF> struct HopWaves { static constexpr int W = WD_HOP_WAVES_LO; };
-template <> struct HopWaves<SF64> { static constexpr int W = WD_HOP_WAVES_64; };
-
-// Job-local block order. With tz > 0 the blocks walk t fastest inside groups of tz z-planes, so a
-// block's t +- 1 neighbours were (or are about to be) loaded by blocks running on the same XCD at
-// nearly the same time, while the site order would put them a whole t-slice apart.
-__device__ __forceinline__ int tiled_block(const HopJob& J, int lb)
-{
-    if (J.tz <= 0) return lb;
-    const int q = lb % J.bpp;
-    int r = lb / J.bpp;
-    const int zz = r % J.tz;
-    r /= J.tz;
-    const int t = r % J.g.T;
-    const int zg = r / J.g.T;
-    return q + J.bpp * ((zg * J.tz + zz) + J.g.Z * t);
-}
-
-// TG: some job of the launch has temporal-gauge links (TG = false compiles the unit-link paths out).
-// NTL: the links are loaded non-temporally, so that they do not evict the neighbour spinors from
-// L2; launches with interleaved systems (links shared through L2) take ordinary loads. A compile-
-// time choice: as a run-time branch the compiler merges the two identical loads and drops the hint.
-template <int SF, int LF, bool DAG, int RED, int FIN, bool STG, bool NTL, bool TG>
-__global__ __launch_bounds__(BLOCK, HopWaves<SF>::W > 0 ? HopWaves<SF>::W : 1) void k_hop(
-    const HopJob* __restrict__ jobs, int njobs, SysState* __restrict__ sys, int gated, int* exec)
-{
-    using T = typename SReal<SF>::T;
-    const int b = WD_XCD_REMAP ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
-    int jx = find_job(jobs, njobs, b);
-    int lb = b - jobs[jx].blk0;
-    if (jobs[jx].ilv > 1) {
-        // interleaved group: find_job returned its last job
-        const int K = jobs[jx].ilv;
-        jx = jx - jobs[jx].ilv_pos + lb % K;
-        lb /= K;
-    }
-    const HopJob& J = jobs[jx];
-    SysState* S = sys + J.sys;
-    if (gated && !((gated >> S->status) & 1)) return;  // gated: mask of the statuses that run
-    if (exec && lb == 0 && threadIdx.x == 0) atomicAdd(exec, 1);  // timing: jobs that did work
-    const int cb0 = tiled_block(J, lb) * BLOCK;
-    const int cb = cb0 + threadIdx.x;
-    __shared__ Stg<SF, STG> stg;
-    int base = 0, nsl = 0;
-    if constexpr (STG) {
-        const int H = J.g.Xh <= STG_H_MAX ? J.g.Xh : 0;
-        base = cb0 - H;
-        nsl = BLOCK + 2 * H;
-        for (int k = threadIdx.x; k < nsl; k += BLOCK) {
-            const int i = base + k;
-            if (i >= 0 && i < J.g.Vh) stage_site<SF>(stg, k, J.in, i);
-        }
-        __syncthreads();
-    }
-    const HopIn<SF, STG> hin{J.in, stg, base, nsl, TG && J.tg != 0};
-    double v[NRED] = {0.0, 0.0, 0.0, 0.0};
-    if (cb < J.g.Vh) {
-        cx<T> acc[12];
-        hop_site<DAG, SF, LF, STG, NTL, T>(J.g, J.parity, cb, hin, J.links, J.lcs, acc);
-        const T c2 = (T)J.c2;
-#pragma unroll
-        for (int k = 0; k < 12; k++) acc[k] = c2 * acc[k];
-        cx<T> x0[12];
-        if (J.x0.p) {
-            load_spinor<SF, T>(J.x0, cb, x0);
-            const T c0 = (T)J.c0;
-#pragma unroll
-            for (int k = 0; k < 12; k++) acc[k] = acc[k] + c0 * x0[k];
-        }
-        if (J.x1.p) {
-            cx<T> x1[12];
-            load_spinor<SF, T>(J.x1, cb, x1);
-            const T c1 = (T)J.c1;
-#pragma unroll
-            for (int k = 0; k < 12; k++) acc[k] = acc[k] + c1 * x1[k];
-        }
-        store_spinor<SF, T, NTL>(J.out, cb, acc);
-        if constexpr (RED == RED_ZDOT) {
-            cx<T> z[12];
-            load_spinor<SF, T>(J.z, cb, z);
-#pragma unroll
-            for (int k = 0; k < 12; k++) {
-                v[0] += (double)z[k].re * acc[k].re + (double)z[k].im * acc[k].im;
-                v[1] += (double)z[k].re * acc[k].im - (double)z[k].im * acc[k].re;
-            }
-        } else if constexpr (RED == RED_OUTX) {
-#pragma unroll
-            for (int k = 0; k < 12; k++) {
-                v[0] += (double)acc[k].re * x0[k].re + (double)acc[k].im * x0[k].im;
-                v[1] += (double)acc[k].re * x0[k].im - (double)acc[k].im * x0[k].re;
-                v[2] += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
-            }
-        } else if constexpr (RED == RED_NORM) {
-#pragma unroll
-            for (int k = 0; k < 12; k++) v[2] += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
-        }
-    }
-    if constexpr (RED != RED_NONE) write_partials<3>(v, S, J.rblk0 + lb);
 }
 
 // ================================================================ sweeps
@@ -1356,35 +1016,6 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const double2* __restrict__ xs, 
 
 // ================================================================ host launchers
 
-static inline dim3 grid1(long nblk) { return dim3((unsigned)nblk); }
-
-#define HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, STG_, TG_)                                                          \
-    if (ntl) hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, STG_, true, TG_>), grid1(nblocks), dim3(BLOCK), 0, s, \
-                                jobs, njobs, sys, gated, exec);                                                    \
-    else hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, STG_, false, TG_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs, \
-                       sys, gated, exec)
-// The kernel does not depend on the finisher run after it (FIN_ names the instantiation only): the
-// launch is chosen by the reduction kind.
-#define HOP_CASE(SF_, LF_, DAG_, RED_, FIN_)                                                                        \
-    if (sf == SF_ && lf == LF_ && dag == DAG_ && red == RED_) {                                                    \
-        const bool stg_ = (SF_ != SF64 ? stage : stage64) != 0;                                                    \
-        if (stg_ && tg) HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, true, !DAG_);                                       \
-        else if (stg_) HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, true, false);                                        \
-        else if (tg) HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, false, !DAG_);                                         \
-        else HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, false, false);                                                 \
-        return hipGetLastError();                                                                                  \
-    }
-#define HOP_REDS(SF_, LF_, DAG_)                                                                                   \
-    HOP_CASE(SF_, LF_, DAG_, RED_NONE, FIN_STORE)                                                                  \
-    HOP_CASE(SF_, LF_, DAG_, RED_NORM, FIN_STORE)                                                                  \
-    HOP_CASE(SF_, LF_, DAG_, RED_ZDOT, FIN_BETA)                                                                   \
-    HOP_CASE(SF_, LF_, DAG_, RED_OUTX, FIN_CHI)
-// the adjoint hops of the normal equations (CG): the iteration's two, plus the FP64 residual's
-#define HOP_DAG_LO(SF_, LF_)                                                                                       \
-    HOP_CASE(SF_, LF_, true, RED_NONE, FIN_STORE)                                                                  \
-    HOP_CASE(SF_, LF_, true, RED_ZDOT, FIN_BETA)
-#define HOP_DAG_64(LF_) HOP_DAG_LO(SF64, LF_) HOP_CASE(SF64, LF_, true, RED_NORM, FIN_STORE)
-
 #define FIN_CASE(NR_, FIN_)                                                                                        \
     if (nr == NR_ && fin == FIN_) {                                                                                \
         hipLaunchKernelGGL((k_finish<NR_, FIN_>), dim3(nfin), dim3(BLOCK), 0, s, fins, sys, gated);               \
@@ -1403,36 +1034,6 @@ hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState
     FIN_CASE(3, FIN_CGA)
     FIN_CASE(3, FIN_CGB)
     FIN_CASE(0, FIN_CGEND)
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
-                      SysState* sys, int gated, hipStream_t s, int* exec, int stage, int tg, int ntl)
-{
-    if (tg && dag) return hipErrorInvalidValue;  // the adjoint hop runs on the caller's links only
-    if (nblocks <= 0) return hipSuccess;
-    if (stage < 0) stage = hop_stage_default();
-    const int stage64 = hop_stage64_default();
-    HOP_REDS(SF64, L64_18, false)
-    HOP_REDS(SF64, L64_12, false)
-    HOP_REDS(SF32, L32_12, false)
-    HOP_REDS(SF32, L16_12, false)
-    HOP_REDS(SF32, LB16_12, false)
-    HOP_REDS(SF16, L32_12, false)
-    HOP_REDS(SF16, L16_12, false)
-    HOP_REDS(SF16, LB16_12, false)
-    HOP_REDS(SF32, L16_8, false)
-    HOP_REDS(SF16, L16_8, false)
-    HOP_DAG_64(L64_18)
-    HOP_DAG_64(L64_12)
-    HOP_DAG_LO(SF32, L32_12)
-    HOP_DAG_LO(SF32, L16_12)
-    HOP_DAG_LO(SF32, LB16_12)
-    HOP_DAG_LO(SF16, L32_12)
-    HOP_DAG_LO(SF16, L16_12)
-    HOP_DAG_LO(SF16, LB16_12)
-    HOP_DAG_LO(SF32, L16_8)
-    HOP_DAG_LO(SF16, L16_8)
     return hipErrorInvalidValue;
 }
 

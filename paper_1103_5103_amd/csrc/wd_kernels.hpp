@@ -9,12 +9,17 @@ enum SweepOp { OP_W = 0, OP_XR = 1, OP_S = 2, OP_SHIFT = 3, OP_INIT = 4, OP_ACC 
                OP_LINCOMB = 9, OP_CGX = 10, OP_CGP = 11, OP_CGPM = 12 };
 
 // exec (may be NULL): incremented once per job that was not gated off. stage: LDS staging of the
-// x/y neighbours in the FP32/FP16 hop (1 on, 0 off, -1 the default of hop_stage_default()).
+// x/y neighbours (1 on, 0 off, -1 the defaults hop_stage_default() / hop_stage64_default()).
 // tg: some job has temporal-gauge links (HopJob::tg); must be 0 for the adjoint hop. ntl:
 // non-temporal link loads (for launches in which no two jobs share links through L2).
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
                       SysState* sys, int gated, hipStream_t s, int* exec = nullptr, int stage = -1, int tg = 0,
                       int ntl = 1);
+// Multi-RHS hop (tables whose jobs have rhs >= 2): kt = mrhs_kt(largest group), 2 or 4 systems per
+// thread at most (0: unsupported group size). Low-precision spinors only.
+int mrhs_kt(int k);
+hipError_t launch_hop_mrhs(int sf, int lf, bool dag, int red, int kt, const HopJob* jobs, int njobs, long nblocks,
+                           SysState* sys, int gated, hipStream_t s, int* exec = nullptr);
 int hop_stage_default();
 int hop_stage64_default();
 hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState* sys, int gated, hipStream_t s);

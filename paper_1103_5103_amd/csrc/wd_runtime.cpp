@@ -157,7 +157,7 @@ char* stage_alloc(size_t n)
     return p;
 }
 
-static int job_blocks_factor(const HopJob& j) { return j.ilv > 1 ? j.ilv : 1; }
+static int job_blocks_factor(const HopJob& j) { return j.ilv > 1 && j.rhs < 2 ? j.ilv : 1; }
 static int job_blocks_factor(const SweepJob&) { return 1; }
 
 template <class J>
@@ -240,7 +240,7 @@ static void run_finish(int nr, int fin, const JobTable<J>& t, SysState* sys, int
 }
 
 void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>& t, SysState* sys, int gated,
-             hipStream_t s, double bytes)
+             hipStream_t s, double bytes, int stage, int ntl_force)
 {
     Timer& T = timer();
     hipEvent_t a = nullptr, b = nullptr;
@@ -263,7 +263,16 @@ void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>&
         link_bytes += (double)j.g.Vh * 8 * link_chunks(lf) * link_chunk_bytes(lf);
     }
     if (link_bytes <= 64.0 * (1 << 20)) ntl = 0;
-    WD_CHECK_HIP(launch_hop(sf, lf, dag, red, fin, t.d(), t.n(), t.nblocks, sys, gated, s, flag, -1, tg, ntl));
+    if (ntl_force >= 0) ntl = ntl_force != 0;
+    if (!t.host.empty() && t.host[0].rhs >= 2) {
+        int kmax = 1;
+        for (auto& j : t.host) kmax = std::max(kmax, j.ilv);
+        const int kt = mrhs_kt(kmax);
+        if (kt == 0 || sf == SF64) throw Error{WD_ERR_UNSUPPORTED, "multi-RHS hop: unsupported group or format"};
+        WD_CHECK_HIP(launch_hop_mrhs(sf, lf, dag, red, kt, t.d(), t.n(), t.nblocks, sys, gated, s, flag));
+    } else {
+        WD_CHECK_HIP(launch_hop(sf, lf, dag, red, fin, t.d(), t.n(), t.nblocks, sys, gated, s, flag, stage, tg, ntl));
+    }
     if (T.on) {
         WD_CHECK_HIP(hipEventRecord(b, s));
         T.pending.push_back({cls, a, b, bytes, (int)(flag - T.dflags), t.n()});

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <sys/stat.h>
 
 #include "wd_host.hpp"
 
@@ -131,15 +132,73 @@ struct SysArray {
 
 static inline int nblk(long n) { return (int)((n + BLOCK - 1) / BLOCK); }
 
-// ---------------------------------------------------------------- block-order autotuner
-// Candidate orders: site order (tz = 0) or t fastest within groups of tz z-planes. Each is timed
-// on the real lattice (one hop with the solver's storage formats); the fastest is kept per
-// (lattice extents, spinor format, link format) for the life of the process. WD_TILE=<tz>
-// overrides the choice.
-static std::map<std::string, int>& tile_cache()
+// ---------------------------------------------------------------- hop autotuner
+// For the hops of one handle in a launch in which nshared systems read its links, the tuner picks
+// the block order (site order, tz = 0, or t fastest within groups of tz z-planes) and the way the
+// systems share the link loads (rhs = 0: one system per thread, systems sharing links in
+// interleaved block pairs; rhs = k >= 2: the multi-RHS hop, k systems per thread). Every candidate
+// is timed on the handle's lattice with min(nshared, 4) systems in the solver's storage formats,
+// each candidate's best of three interleaved passes counts. The choice is kept per (device
+// architecture, lattice extents, formats, temporal gauge, systems) for the process and in a text
+// file ($WD_TUNE_CACHE, else $HOME/.cache/wdirac/hop_tune.txt) that later processes read first.
+struct HopChoice {
+    int tz = 0;
+    int rhs = 0;
+};
+
+static std::string arch_name()
 {
-    static std::map<std::string, int> c;
+    static const std::string a = [] {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return std::string("unknown");
+        const std::string s(p.gcnArchName);
+        return s.substr(0, s.find(':'));
+    }();
+    return a;
+}
+
+static std::string tune_path()
+{
+    if (const char* e = std::getenv("WD_TUNE_CACHE")) return e;
+    const char* h = std::getenv("HOME");
+    return h ? std::string(h) + "/.cache/wdirac/hop_tune.txt" : std::string();
+}
+
+static std::map<std::string, HopChoice>& tune_cache()
+{
+    static std::map<std::string, HopChoice> c;
+    static bool loaded = false;
+    if (!loaded) {
+        loaded = true;
+        const std::string path = tune_path();
+        if (FILE* f = path.empty() ? nullptr : std::fopen(path.c_str(), "r")) {
+            char key[256];
+            int tz, rhs;
+            while (std::fscanf(f, "%255s %d %d", key, &tz, &rhs) == 3) c[key] = HopChoice{tz, rhs};
+            std::fclose(f);
+        }
+    }
     return c;
+}
+
+static void tune_store(const std::string& key, HopChoice ch)
+{
+    tune_cache()[key] = ch;
+    const std::string path = tune_path();
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        // create the directory and its parent if missing (errors are ignored: the file is a cache)
+        const std::string dir = path.substr(0, slash);
+        const size_t up = dir.rfind('/');
+        if (up != std::string::npos && up > 0) (void)mkdir(dir.substr(0, up).c_str(), 0755);
+        (void)mkdir(dir.c_str(), 0755);
+    }
+    if (FILE* f = std::fopen(path.c_str(), "a")) {
+        std::fprintf(f, "%s %d %d\n", key.c_str(), ch.tz, ch.rhs);
+        std::fclose(f);
+    }
 }
 
 static bool tile_valid(const Geo& g, int tz)
@@ -168,73 +227,92 @@ static int link_policy(wd_gauge* g, int lf, bool shared)
     return !shared && bytes > 64.0 * (1 << 20);
 }
 
-int tune_tile(wd_gauge* g, int sf, int lf, hipStream_t st, bool shared = false)
+HopChoice tune_hop(wd_gauge* g, int sf, int lf, hipStream_t st, int nshared)
 {
     const Geo& G = g->geo;
-    const int ntl = link_policy(g, lf, shared);
-    if (const char* env = std::getenv("WD_TILE")) {
-        int tz = std::atoi(env);
-        return tile_valid(G, tz) ? tz : 0;
+    const int nc = std::max(1, std::min(nshared, 4));
+    std::vector<HopChoice> cands;
+    for (int rhs : {0, 2, 4}) {
+        if (rhs > 0 && (sf == SF64 || nc < 2 || (rhs == 4 && nc < 3))) continue;
+        for (int tz : {0, 2, 4, 8, 16})
+            if (tile_valid(G, tz)) cands.push_back(HopChoice{tz, rhs});
     }
-    if ((G.Xh * G.Y) % BLOCK != 0 || G.Vh < (1 << 16)) return 0;
-    char key[96];
-    std::snprintf(key, sizeof(key), "%d.%d.%d.%d.%d.%d.%d", G.X, G.Y, G.Z, G.T, sf, lf, ntl);
-    auto it = tile_cache().find(key);
-    if (it != tile_cache().end()) return it->second;
+    if (cands.size() == 1) return cands[0];
+    char key[160];
+    std::snprintf(key, sizeof(key), "%s|%dx%dx%dx%d|sf%d|lf%d|tg%d|n%d", arch_name().c_str(), G.X, G.Y, G.Z, G.T, sf, lf,
+                  (int)g->tg, nc);
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) return it->second;
     g->ensure_slinks(lf, st);
-    Field in = g->field("tune.in", sf, 1), out = g->field("tune.out", sf, 1);
-    SysState* dummy = (SysState*)g->rawbuf("apply.sys", sizeof(SysState));
+    std::vector<Field> in(nc), out(nc);
+    for (int k = 0; k < nc; k++) {
+        in[k] = g->field("tune.in" + std::to_string(k), sf, 1);
+        out[k] = g->field("tune.out" + std::to_string(k), sf, 1);
+    }
+    SysState* dummy = (SysState*)g->rawbuf("tune.sys", sizeof(SysState) * nc);
+    const int ntl = link_policy(g, lf, nc > 1);
+    std::vector<JobTable<HopJob>> tabs(cands.size());
+    for (size_t c = 0; c < cands.size(); c++) {
+        for (int k = 0; k < nc; k++) {
+            HopJob j = hop_job(G, 1, k, in[k].all(), out[k].all(), g->slk(lf, 1), g->lcs(), 1.0);
+            j.tg = g->tg;
+            j.rhs = cands[c].rhs;
+            set_tile(j, cands[c].tz);
+            tabs[c].host.push_back(j);
+        }
+        layout(tabs[c]);
+        tabs[c].upload(st);
+    }
+    auto launch = [&](const JobTable<HopJob>& t) {
+        if (t.host[0].rhs >= 2) {
+            int kmax = 1;
+            for (auto& j : t.host) kmax = std::max(kmax, j.ilv);
+            WD_CHECK_HIP(launch_hop_mrhs(sf, lf, false, RED_NONE, mrhs_kt(kmax), t.d(), t.n(), t.nblocks, dummy, 0, st));
+        } else {
+            WD_CHECK_HIP(launch_hop(sf, lf, false, RED_NONE, FIN_STORE, t.d(), t.n(), t.nblocks, dummy, 0, st, nullptr, -1,
+                                    t.host[0].tg, ntl));
+        }
+    };
     hipEvent_t e0, e1;
     WD_CHECK_HIP(hipEventCreate(&e0));
     WD_CHECK_HIP(hipEventCreate(&e1));
     // three interleaved passes over the candidates, each candidate's best pass counts (a single
-    // pass let the clock and cache state of the moment decide between orders within a few %)
-    std::vector<int> tzs;
-    std::vector<JobTable<HopJob>> tabs;
-    for (int tz : {0, 2, 4, 8, 16}) {
-        if (!tile_valid(G, tz)) continue;
-        JobTable<HopJob> t;
-        HopJob j = hop_job(G, 1, 0, in.all(), out.all(), g->slk(lf, 1), g->lcs(), 1.0);
-        j.tg = g->tg;
-        set_tile(j, tz);
-        t.host.push_back(j);
-        layout(t);
-        t.upload(st);
-        tzs.push_back(tz);
-        tabs.push_back(std::move(t));
-    }
-    std::vector<float> cand_ms(tzs.size(), 1e30f);
+    // pass let the clock and cache state of the moment decide within a few %)
+    std::vector<float> cand_ms(cands.size(), 1e30f);
     for (int pass = 0; pass < 3; pass++)
-        for (size_t c = 0; c < tzs.size(); c++) {
-            const JobTable<HopJob>& t = tabs[c];
-            const int tg = t.host[0].tg;
-            WD_CHECK_HIP(launch_hop(sf, lf, false, RED_NONE, FIN_STORE, t.d(), t.n(), t.nblocks, dummy, 0, st, nullptr, -1,
-                                    tg, ntl));
+        for (size_t c = 0; c < cands.size(); c++) {
+            launch(tabs[c]);
             WD_CHECK_HIP(hipEventRecord(e0, st));
-            for (int w = 0; w < 4; w++)
-                WD_CHECK_HIP(launch_hop(sf, lf, false, RED_NONE, FIN_STORE, t.d(), t.n(), t.nblocks, dummy, 0, st, nullptr,
-                                        -1, tg, ntl));
+            for (int w = 0; w < 4; w++) launch(tabs[c]);
             WD_CHECK_HIP(hipEventRecord(e1, st));
             WD_CHECK_HIP(hipEventSynchronize(e1));
             float ms = 0;
             WD_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
-            cand_ms[c] = std::min(cand_ms[c], ms * 6.0f / 4.0f);
+            cand_ms[c] = std::min(cand_ms[c], ms / (4.0f * nc));
         }
-    int best = 0;
-    float best_ms = 1e30f;
-    for (size_t c = 0; c < tzs.size(); c++)
-        if (cand_ms[c] < best_ms) {
-            best_ms = cand_ms[c];
-            best = tzs[c];
-        }
+    size_t best = 0;
+    for (size_t c = 1; c < cands.size(); c++)
+        if (cand_ms[c] < cand_ms[best]) best = c;
     WD_CHECK_HIP(hipEventDestroy(e0));
     WD_CHECK_HIP(hipEventDestroy(e1));
-    if (std::getenv("WD_VERBOSE"))
-        std::fprintf(stderr, "wdirac: block order for %s: tz=%d (%.1f us per hop)\n", key, best, best_ms * 1e3 / 6);
-    g->ws.erase("tune.in");
-    g->ws.erase("tune.out");
-    tile_cache()[key] = best;
-    return best;
+    if (std::getenv("WD_VERBOSE")) {
+        for (size_t c = 0; c < cands.size(); c++)
+            std::fprintf(stderr, "wdirac: tune %s: tz=%d rhs=%d %.1f us per system-hop\n", key, cands[c].tz, cands[c].rhs,
+                         cand_ms[c] * 1e3);
+        std::fprintf(stderr, "wdirac: tune %s: chose tz=%d rhs=%d\n", key, cands[best].tz, cands[best].rhs);
+    }
+    for (int k = 0; k < nc; k++) {
+        g->ws.erase("tune.in" + std::to_string(k));
+        g->ws.erase("tune.out" + std::to_string(k));
+    }
+    tune_store(key, cands[best]);
+    return cands[best];
+}
+
+// block order alone, for launches in which the handle's links are not shared (or interleaved pairs)
+int tune_tile(wd_gauge* g, int sf, int lf, hipStream_t st, bool shared = false)
+{
+    return tune_hop(g, sf, lf, st, shared ? 2 : 1).tz;
 }
 
 static HopJob hop_job(const Geo& g, int parity, int sys, const SpinorRef& in, const SpinorRef& out,
@@ -254,37 +332,26 @@ static HopJob hop_job(const Geo& g, int parity, int sys, const SpinorRef& in, co
     return j;
 }
 
-// Interleaved block order for hop jobs that share their links (on by default; the environment
-// variable WD_HOP_ILV=0 turns it off for comparisons).
-static bool interleave_on()
-{
-    static const bool v = [] {
-        const char* e = std::getenv("WD_HOP_ILV");
-        return e ? std::atoi(e) != 0 : true;
-    }();
-    return v;
-}
-
-// largest interleaved group (environment variable WD_HOP_ILV_MAX, default 2: pairs of systems
-// share the link loads while the neighbour spinors of the two still fit the L2 reuse window;
-// measured at 32^3x64 with 8 systems, the hop takes 660 / 673 / 712 / 693 us for groups of
-// 2 / 3 / 4 / 8)
-static int interleave_max()
-{
-    static const int v = [] {
-        const char* e = std::getenv("WD_HOP_ILV_MAX");
-        const int k = e ? std::atoi(e) : 2;
-        return k < 1 ? 1 : (k > 64 ? 64 : k);
-    }();
-    return v;
-}
+// Hop jobs that share their links (same gauge field and parity) run in interleaved block groups of
+// at most kIlvMax systems: pairs share the link loads while the neighbour spinors of both still fit
+// the L2 reuse window (measured at 32^3x64 with 8 systems: 660 / 673 / 712 / 693 us per hop for
+// groups of 2 / 3 / 4 / 8).
+constexpr int kIlvMax = 2;
+static bool interleave_on() { return true; }
+static int interleave_max() { return kIlvMax; }
 
 static bool same_links(const HopJob& a, const HopJob& b)
 {
     return a.links == b.links && a.parity == b.parity && a.g.Vh == b.g.Vh && a.g.X == b.g.X && a.g.Y == b.g.Y &&
-           a.g.Z == b.g.Z && a.g.T == b.g.T && a.nblk == b.nblk && a.tz == b.tz && a.bpp == b.bpp;
+           a.g.Z == b.g.Z && a.g.T == b.g.T && a.nblk == b.nblk && a.tz == b.tz && a.bpp == b.bpp && a.rhs == b.rhs &&
+           a.tg == b.tg && a.lcs == b.lcs;
 }
 static bool same_links(const SweepJob&, const SweepJob&) { return false; }
+// largest group of jobs sharing links: rhs systems per thread for the multi-RHS hop, else kIlvMax
+static int group_max(const HopJob& j) { return j.rhs >= 2 ? j.rhs : interleave_max(); }
+static int group_max(const SweepJob&) { return 1; }
+static int group_blocks(const HopJob& j, int K) { return j.rhs >= 2 ? j.nblk : K * j.nblk; }
+static int group_blocks(const SweepJob& j, int K) { return K * j.nblk; }
 static void set_group(HopJob& j, int k, int pos)
 {
     j.ilv = k;
@@ -303,7 +370,7 @@ static void layout(JobTable<J>& t)
     for (size_t i = 0; i < n;) {
         size_t k = i + 1;
         if (interleave_on())
-            while (k < n && (int)(k - i) < interleave_max() && same_links(t.host[i], t.host[k])) k++;
+            while (k < n && (int)(k - i) < group_max(t.host[i]) && same_links(t.host[i], t.host[k])) k++;
         const int K = (int)(k - i);
         for (size_t m = i; m < k; m++) {
             J& j = t.host[m];
@@ -312,7 +379,7 @@ static void layout(JobTable<J>& t)
             j.rblk0 = group[j.sys];
             group[j.sys] += j.nblk;
         }
-        b += K * t.host[i].nblk;
+        b += group_blocks(t.host[i], K);
         i = k;
     }
     for (auto& j : t.host) j.rnblk = group[j.sys];
@@ -346,6 +413,42 @@ static double sweep_bytes(const JobTable<SweepJob>& t, double per_site)
     double n = 0;
     for (auto& j : t.host) n += (double)j.n;
     return n * per_site;
+}
+
+// Jobs that read the same links made consecutive (stable in the systems' order), so that layout()
+// can group them; one job per system and table, so reduction groups are unaffected.
+static void group_by_links(JobTable<HopJob>& t)
+{
+    std::stable_sort(t.host.begin(), t.host.end(), [](const HopJob& a, const HopJob& b) {
+        return a.links != b.links ? (uintptr_t)a.links < (uintptr_t)b.links : a.parity < b.parity;
+    });
+}
+
+// Tuned hop choices for a batch of systems: per system the block orders of its handle (low
+// precision, FP64) for the number of systems in the batch that share the handle's links, and one
+// multi-RHS mode for the low-precision launches (a launch runs a single kernel): the mode tuned for
+// the handle that carries the most work.
+template <class Sys>
+static int tune_shared_hops(const std::vector<Sys>& S, int SFL, int LFL, int L64, hipStream_t st, std::vector<int>& tile_lo,
+                            std::vector<int>& tile_64)
+{
+    const int n = (int)S.size();
+    std::map<wd_gauge*, int> count;
+    for (auto& e : S) count[e.g]++;
+    int rhs = 0;
+    double most = -1;
+    for (int i = 0; i < n; i++) {
+        const int c = interleave_on() ? count[S[i].g] : 1;
+        const HopChoice lo = tune_hop(S[i].g, SFL, LFL, st, c);
+        tile_lo[i] = lo.tz;
+        tile_64[i] = tune_hop(S[i].g, SF64, L64, st, c).tz;
+        const double work = (double)S[i].g->geo.Vh * c;
+        if (work > most) {
+            most = work;
+            rhs = lo.rhs;
+        }
+    }
+    return rhs;
 }
 
 // ================================================================ even-odd BiCGstab (batched)
@@ -413,15 +516,9 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
                                                 "the operator; solve with mixed = 0"};
     const double t_start = now_s();
 
+    // systems on the same gauge field share link loads (multi-RHS hop or interleaved block pairs)
     std::vector<int> tile_lo(n), tile_64(n);
-    for (int i = 0; i < n; i++) {
-        // systems on the same gauge field form interleaved groups (links shared through L2)
-        bool shared = false;
-        for (int k = 0; k < n; k++) shared = shared || (k != i && S[k].g == S[i].g);
-        shared = shared && interleave_on();
-        tile_lo[i] = tune_tile(S[i].g, SFL, LFL, st, shared);
-        tile_64[i] = tune_tile(S[i].g, SF64, L64, st, shared);
-    }
+    const int rhs_lo = tune_shared_hops(S, SFL, LFL, L64, st, tile_lo, tile_64);
     for (auto& e : S) {
         e.g->ensure_slinks(LFL, st);
         e.g->ensure_slinks(L64, st);
@@ -558,9 +655,13 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
     for (auto* t : {&Hhb, &Hx1, &Hx2, &Hrec})
         for (auto& j : t->host) set_tile(j, tile_64[j.sys]);
     for (auto* t : {&H1, &H2, &H3, &H4})
-        for (auto& j : t->host) set_tile(j, tile_lo[j.sys]);
+        for (auto& j : t->host) {
+            set_tile(j, tile_lo[j.sys]);
+            j.rhs = rhs_lo;
+        }
     for (auto* t : {&Hhb, &Hx1, &Hx2, &Hrec, &H1, &H2, &H3, &H4}) {
         for (auto& j : t->host) j.tg = S[j.sys].g->tg;  // solver links of a temporal-gauge handle
+        group_by_links(*t);
         layout(*t);
     }
     for (auto* t : {&Nb, &Bp, &InitFirst, &InitRel, &InitRestart, &Acc, &SW, &SXR, &SS}) layout(*t);
@@ -765,7 +866,8 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         EoSys& e = S[i];
         if (e.t1 == 0) e.t1 = now_s();
         e.iters = sys.h[i].iter;
-        e.true_rel = (e.src.bb > 0 && e.rr_true >= 0) ? std::sqrt(e.rr_true) / (e.a * std::sqrt(e.src.bb)) : 0.0;
+        if (!std::isfinite(e.src.bb) || e.final_status == WD_ERR_NAN) e.true_rel = std::nan("");
+        else e.true_rel = (e.src.bb > 0 && e.rr_true >= 0) ? std::sqrt(e.rr_true) / (e.a * std::sqrt(e.src.bb)) : 0.0;
     }
 }
 
@@ -991,7 +1093,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
             for (int i = 0; i < nk; i++) {
                 stats[i].iters = i == base ? iters : (sh[shift_of[i]].active ? iters : sh[shift_of[i]].conv_iter);
                 stats[i].reliable_updates = 0;
-                stats[i].true_rel_res = bb > 0 ? std::sqrt(rs.h[i].red[2] / bb) : 0.0;
+                stats[i].true_rel_res = !std::isfinite(bb) ? std::nan("") : bb > 0 ? std::sqrt(rs.h[i].red[2] / bb) : 0.0;
                 stats[i].status = status;
                 stats[i].seconds = t1 - t0;
             }
@@ -1064,6 +1166,94 @@ wd_status solve_batch(int nsys, const wd_system* sys, const wd_solver_params& P,
         if (S[i].final_status != WD_OK && worst == WD_OK) worst = (wd_status)S[i].final_status;
     }
     return worst;
+}
+
+// The even-odd operator in the solvers' storage formats, hop variants chosen by the caller: out_o =
+// D_oe in_e (first hop, stored), out_e = a^2 in_e - 1/4 D_eo out_o (second hop with the epilogue of
+// v.red); the adjoint hops with v.dagger. Each of v.copies systems has its own fields and its own
+// reduction group; systems on one gauge field share link loads (interleaved groups) as in the
+// batched solvers.
+wd_status apply_prec(wd_gauge* g, double kappa, double* out, const double* in, const wd_solver_params& P,
+                     const wd_op_variant& v, double* dots, hipStream_t st)
+{
+    WD_REQUIRE(kappa > 0, "kappa must be positive");
+    WD_REQUIRE(v.red >= WD_RED_NONE && v.red <= WD_RED_NORM, "unknown reduction");
+    WD_REQUIRE(v.copies >= 1 && v.copies <= 64, "copies must be in 1..64");
+    WD_REQUIRE(v.stage >= -1 && v.stage <= 1 && v.nontemporal >= -1 && v.nontemporal <= 1, "bad stage / nontemporal");
+    WD_REQUIRE(v.tile >= -1, "bad tile");
+    WD_REQUIRE(v.rhs_per_thread >= -1 && v.rhs_per_thread <= 4, "rhs_per_thread must be in -1..4");
+    const int SFL = P.mixed ? spinor_fmt_of(P.spinor_store) : SF64;
+    const int LFL = P.mixed ? link_fmt_of(P.link_store, P.recon) : g->f64_links();
+    if (v.dagger && !(v.red == WD_RED_NONE || v.red == WD_RED_ZDOT || (SFL == SF64 && v.red == WD_RED_NORM)))
+        throw Error{WD_ERR_UNSUPPORTED, "the adjoint hops fuse no <out, in> reduction (and |out|^2 in FP64 only)"};
+    if (SFL == SF64 && LFL != L64_12 && LFL != L64_18)
+        throw Error{WD_ERR_UNSUPPORTED, "FP64 spinors take FP64 links"};
+    if (SFL != SF64 && (LFL == L64_12 || LFL == L64_18))
+        throw Error{WD_ERR_UNSUPPORTED, "FP64 links take FP64 spinors"};
+    if (link_recon12(LFL) && g->recon_err > 1e-6)
+        throw Error{WD_ERR_UNSUPPORTED, "links are not SU(3): the 12-real formats would change the operator"};
+    g->ensure_slinks(LFL, st);
+    const Geo& G = g->geo;
+    const int K = v.copies;
+    const double a = 1.0 / (2.0 * kappa);
+    const long V = g->V;
+    std::vector<Field> F(K), Tm(K), O(K);
+    for (int k = 0; k < K; k++) {
+        F[k] = g->field("ap.in" + std::to_string(k), SFL, 2);
+        Tm[k] = g->field("ap.t" + std::to_string(k), SFL, 1);
+        O[k] = g->field("ap.out" + std::to_string(k), SFL, 1);
+    }
+    SysArray sys;
+    sys.alloc(K, g->raw["ap.sys"]);
+    const size_t pstride = (size_t)NRED * (2 * G.stride / BLOCK + 1);
+    double* part = (double*)g->rawbuf("ap.partials", sizeof(double) * pstride * K);
+    for (int k = 0; k < K; k++) {
+        std::memset(&sys.h[k], 0, sizeof(SysState));
+        sys.h[k].partials = part + pstride * k;
+    }
+    sys.upload(st);
+    HopChoice ch;
+    if (v.tile < 0 || v.rhs_per_thread < 0) ch = tune_hop(g, SFL, LFL, st, K);
+    const int tz = v.tile < 0 ? ch.tz : (tile_valid(G, v.tile) ? v.tile : 0);
+    const int rhs = v.rhs_per_thread < 0 ? ch.rhs : (v.rhs_per_thread <= 1 ? 0 : v.rhs_per_thread);
+    if (rhs >= 2 && (SFL == SF64 || v.red == WD_RED_NORM))
+        throw Error{WD_ERR_UNSUPPORTED, "the multi-RHS hop takes FP32 / FP16 spinors and no |out|^2-only reduction"};
+    const bool tg = g->tg && !v.dagger;  // the adjoint hops read every stored link
+    JobTable<HopJob> H1, H2;
+    for (int k = 0; k < K; k++) {
+        HopJob j = hop_job(G, 1, k, F[k].half(0), Tm[k].all(), g->slk(LFL, 1), g->lcs(), 1.0);
+        j.tg = tg;
+        j.rhs = rhs;
+        set_tile(j, tz);
+        H1.host.push_back(j);
+        j = hop_job(G, 0, k, Tm[k].all(), O[k].all(), g->slk(LFL, 0), g->lcs(), -0.25);
+        j.tg = tg;
+        j.rhs = rhs;
+        j.x0 = F[k].half(0);
+        j.c0 = a * a;
+        j.z = F[k].half(0);
+        set_tile(j, tz);
+        H2.host.push_back(j);
+    }
+    layout(H1);
+    layout(H2);
+    upload_tables(st, g->raw["ap.tables"], {&H1, &H2});
+    for (int k = 0; k < K; k++)
+        WD_CHECK_HIP(launch_pack_spinor(SFL, in + (size_t)k * V * 24, G, F[k].half(0), F[k].half(1), 0, 1.0, st, g->gm()));
+    const int ext[4] = {1, 2, 1, 1};  // epilogue fields read by the second hop (x0, and z for ZDOT)
+    run_hop(SFL, LFL, v.dagger != 0, RED_NONE, FIN_STORE, H1, sys.d(), 0, st, hop_bytes(H1, SFL, LFL, 0), v.stage,
+            v.nontemporal);
+    // the hop kernel depends on the reduction kind only; its finisher here just stores the sums
+    run_hop(SFL, LFL, v.dagger != 0, v.red, FIN_STORE, H2, sys.d(), 0, st, hop_bytes(H2, SFL, LFL, ext[v.red]),
+            v.stage, v.nontemporal);
+    for (int k = 0; k < K; k++)
+        WD_CHECK_HIP(
+            launch_unpack_spinor(SFL, out + (size_t)k * V * 24, G, O[k].all(), Tm[k].all(), 0, 1.0, st, g->gm()));
+    sys.download(st);
+    if (dots)
+        for (int k = 0; k < K; k++)
+            for (int i = 0; i < 3; i++) dots[3 * k + i] = sys.h[k].red[i];
+    return WD_OK;
 }
 
 // <a, v_j> for every view v_j (full FP64 fields of handle g), through the device multi-dot
@@ -1411,15 +1601,9 @@ static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream
                 throw Error{WD_ERR_UNSUPPORTED, "links are not SU(3): the 12-real low-precision formats would change "
                                                 "the operator; solve with mixed = 0"};
     const double t_start = now_s();
+    // systems on the same gauge field share link loads (multi-RHS hop or interleaved block pairs)
     std::vector<int> tile_lo(n), tile_64(n);
-    for (int i = 0; i < n; i++) {
-        // systems on the same gauge field form interleaved groups (links shared through L2)
-        bool shared = false;
-        for (int k = 0; k < n; k++) shared = shared || (k != i && S[k].g == S[i].g);
-        shared = shared && interleave_on();
-        tile_lo[i] = tune_tile(S[i].g, SFL, LFL, st, shared);
-        tile_64[i] = tune_tile(S[i].g, SF64, L64, st, shared);
-    }
+    const int rhs_lo = tune_shared_hops(S, SFL, LFL, L64, st, tile_lo, tile_64);
     for (auto& e : S) {
         e.g->ensure_slinks(LFL, st);
         e.g->ensure_slinks(L64, st);
@@ -1545,12 +1729,18 @@ static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream
     for (auto* t : {&Hx1, &Hx2, &Hx3, &Hx4})
         for (auto& j : t->host) set_tile(j, tile_64[j.sys]);
     for (auto* t : {&H1, &H2, &H3, &H4})
-        for (auto& j : t->host) set_tile(j, tile_lo[j.sys]);
+        for (auto& j : t->host) {
+            set_tile(j, tile_lo[j.sys]);
+            j.rhs = rhs_lo;
+        }
     // the forward hops skip the unit time links of a temporal-gauge handle; the adjoint hops read
     // every link (all of them are stored)
     for (auto* t : {&Hx1, &Hx2, &H1, &H2})
         for (auto& j : t->host) j.tg = S[j.sys].g->tg;
-    for (auto* t : {&Hx1, &Hx2, &Hx3, &Hx4, &H1, &H2, &H3, &H4}) layout(*t);
+    for (auto* t : {&Hx1, &Hx2, &Hx3, &Hx4, &H1, &H2, &H3, &H4}) {
+        group_by_links(*t);
+        layout(*t);
+    }
     for (auto* t : {&Nb, &Bs, &Acc, &InitFirst, &InitRel, &InitRestart, &SX, &SP}) layout(*t);
     upload_tables(st, S[0].g->raw["cg.tables"],
                   {&Hx1, &Hx2, &Hx3, &Hx4, &H1, &H2, &H3, &H4, &Nb, &Bs, &Acc, &InitFirst, &InitRel, &InitRestart,
@@ -1718,7 +1908,8 @@ static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream
         CgSys& e = S[i];
         if (e.t1 == 0) e.t1 = now_s();
         e.iters = sys.h[i].iter;
-        e.true_rel = (e.be2 > 0 && e.rr_true >= 0) ? std::sqrt(e.rr_true / e.be2) : 0.0;
+        if (!std::isfinite(e.be2) || e.final_status == WD_ERR_NAN) e.true_rel = std::nan("");
+        else e.true_rel = (e.be2 > 0 && e.rr_true >= 0) ? std::sqrt(e.rr_true / e.be2) : 0.0;
     }
 }
 
@@ -1957,7 +2148,7 @@ static wd_status cgm_solve(wd_gauge* g, double kappa, int n, const double* sigma
             for (int i = 0; i < n; i++) {
                 stats[i].iters = i == base ? iters : (sh[shift_of[i]].active ? iters : sh[shift_of[i]].conv_iter);
                 stats[i].reliable_updates = 0;
-                stats[i].true_rel_res = bb > 0 ? std::sqrt(rs.h[i].red[2] / bb) : 0.0;
+                stats[i].true_rel_res = !std::isfinite(bb) ? std::nan("") : bb > 0 ? std::sqrt(rs.h[i].red[2] / bb) : 0.0;
                 stats[i].status = status;
                 stats[i].seconds = t1 - t0;
             }

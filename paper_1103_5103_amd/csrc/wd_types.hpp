@@ -111,6 +111,10 @@ struct HopJob {
     int ilv_pos;         // position of this job in its group
     int tg;              // links in temporal gauge: the time links are the unit matrix except
                          // those leaving the last time slice (not loaded, not multiplied)
+    // rhs >= 2: the group is run by the multi-RHS hop instead (k_hop_mrhs): one thread per output
+    // site applies the hop to all ilv (<= rhs) systems of the group, loading each link once; the
+    // group then spans nblk blocks rather than ilv * nblk. Every job of a launch has the same mode.
+    int rhs;
 };
 
 // Roles of the fields of a sweep job

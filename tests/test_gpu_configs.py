@@ -47,6 +47,36 @@ def test_apply_full_size(big):
     assert np.linalg.norm(out - ref) / np.linalg.norm(ref) < 1e-14
 
 
+@pytest.mark.parametrize("fmt", ["f32/f16", "f32/bf16", "f16/f16"])
+def test_lowprec_operator_full_size(big, fmt):
+    """The solvers' low-precision even-odd operator at 32^3x64, in the launch configuration the
+    benchmark times (tuned block order, non-temporal loads), against the oracle's M_prec and
+    hopping term site by site (tolerances as in test_gpu_lowprec: 1e-2 FP16, 2e-2 BF16, relative
+    to the RMS site norm)."""
+    dims, U, b, g = big
+    spinor, links = fmt.split("/")
+    tol = 2e-2 if "bf16" in fmt else 1e-2
+    kappa = 0.134
+    odd = oracle.parity_mask(dims)
+    pe = b.copy()
+    pe[odd] = 0
+    ref = oracle.mprec(U, kappa, pe)
+    ref[odd] = oracle.hopping(U, pe)[odd]
+    for red in ("none", "zdot", "outx"):
+        out, dots = wd.wd_apply_prec(g, kappa, _t(b), p=wd.params(spinor=spinor, links=links),
+                                     v=wd.op_variant(red=red))
+        out = _n(out)
+        for name, m in (("even", ~odd), ("odd", odd)):
+            d = np.linalg.norm((out[m] - ref[m]).reshape(-1, 12), axis=1)
+            scale = np.sqrt(np.mean(np.linalg.norm(ref[m].reshape(-1, 12), axis=1) ** 2))
+            _say("32^3x64 operator", fmt, red, name, "max", d.max() / scale, "rms", np.sqrt(np.mean(d ** 2)) / scale)
+            assert d.max() / scale < tol
+        if red == "outx":
+            o = out[~odd].reshape(-1)
+            assert abs(dots[0, 2] - np.vdot(o, o).real) < tol * np.vdot(o, o).real
+        del out
+
+
 def test_mixed_solve_full_size_bench_config(big):
     """The benchmark's sequential mixed solve (FP32 spinors, FP16 links, delta 1e-3, poly guess)
     for the lightest and heaviest masses of the 8."""

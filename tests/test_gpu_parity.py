@@ -33,6 +33,14 @@ def _say(*a):
     print(*a, flush=True)
 
 
+def mixed_iteration_bound(n_ref, reliable):
+    """Iterations a mixed-precision solve may take against the oracle's FP64 even-odd BiCGstab on
+    the same system: each FP64 reliable update replaces the iterated residual by the true one,
+    which costs the Krylov space up to about one iteration, and low-precision rounding up to a
+    quarter of the iterations more."""
+    return int(1.25 * n_ref) + reliable + 2
+
+
 # ------------------------------------------------------------------ operator
 
 @pytest.mark.parametrize("dims,anti", [((2, 2, 2, 2), 1), ((4, 4, 4, 4), 1), ((4, 2, 6, 4), 1), ((4, 4, 4, 8), 0),
@@ -133,10 +141,14 @@ def test_bicgstab_eo_mixed(dims, spinor, links, tg):
     kappa = 0.13
     x, st = wd.bicgstab_solve(g, kappa, _t(b), p=wd.params(tol=1e-8, spinor=spinor, links=links))
     res = oracle.true_residual(U, kappa, _n(x), b)
-    _say("eo mixed", dims, spinor, links, tg, st, "oracle residual", res)
+    _, n_ref, _, _ = oracle.bicgstab_eo(U, kappa, b, tol=1e-8)
+    _say("eo mixed", dims, spinor, links, tg, st, "oracle residual", res, "oracle FP64 iterations", n_ref)
     assert st["status"] == 0
     assert res < 1e-8
     assert st["reliable_updates"] >= 1
+    # a wrong low-precision operator is corrected by the FP64 updates only at the cost of many
+    # more iterations: hold the count near the oracle's FP64 even-odd count
+    assert st["iters"] <= mixed_iteration_bound(n_ref, st["reliable_updates"]), (st, n_ref)
     g.close()
 
 
@@ -471,6 +483,66 @@ def test_error_codes():
     g.close()
 
 
+def test_nan_source_reports_nan():
+    """A NaN in the source (forced from the host) ends every method with WD_ERR_NAN and a NaN
+    residual in the stats, without iterating."""
+    dims = (4, 4, 4, 8)
+    U = li.random_links(dims, 1.0, 1041)
+    b = li.gaussian_field(dims, 2041)
+    b[1, 2, 3, 0, 0, 2] = np.nan  # an even site: the normal equations read the even sites only
+    g = wd.wd_gauge_create(_t(U))
+    bd = _t(b)
+    for p in (wd.params(), wd.params(spinor="f16"), wd.params(mixed=False), wd.params(mixed=False, eo=False),
+              wd.params(defect_correction=True)):
+        x, st = wd.bicgstab_solve(g, 0.12, bd, p=p, raise_on_fail=False)
+        _say("NaN source", st)
+        assert st["status"] == wd._lib.WD_ERR_NAN and np.isnan(st["true_rel_res"]), st
+    with pytest.raises(wd.WdError) as e:
+        wd.bicgstab_solve(g, 0.12, bd)
+    assert e.value.code == wd._lib.WD_ERR_NAN
+    kappas = [0.12, 0.124, 0.128]
+    for method in (wd.WD_METHOD_SEQUENTIAL, wd.WD_METHOD_BATCHED, wd.WD_METHOD_MULTISHIFT):
+        p = wd.params(mixed=False, eo=False) if method == wd.WD_METHOD_MULTISHIFT else wd.params()
+        xs, sts = wd.wd_multimass_solve(g, kappas, bd, method=method, p=p, raise_on_fail=False)
+        _say("NaN source, method", method, sts)
+        assert all(s["status"] == wd._lib.WD_ERR_NAN and np.isnan(s["true_rel_res"]) for s in sts), sts
+    for method in (wd.WD_METHOD_SEQUENTIAL, wd.WD_METHOD_MULTISHIFT):
+        p = wd.params(mixed=method == wd.WD_METHOD_SEQUENTIAL)
+        xs, sts = wd.wd_normal_solve(g, 0.12, [0.0, 1.0], bd, method=method, p=p, raise_on_fail=False)
+        _say("NaN source, normal equations", method, sts)
+        assert all(s["status"] == wd._lib.WD_ERR_NAN and np.isnan(s["true_rel_res"]) for s in sts), sts
+    g.close()
+
+
+def test_exact_zero_mode_ends_without_convergence():
+    """U = 1 with periodic time and kappa = 1/8: the constant spinors are exact zero modes of M
+    (free field at p = 0: M = 1/(2 kappa) - 4 = 0), so a Gaussian source has no solution. Every
+    solver must stop with WD_ERR_NOCONV or WD_ERR_BREAKDOWN (after its restarts), stats filled,
+    the reported residual finite and far above the tolerance."""
+    dims = (4, 4, 4, 4)
+    unit = np.zeros((4,) + dims[::-1] + (3, 3), dtype=np.complex128)
+    unit[..., 0, 0] = unit[..., 1, 1] = unit[..., 2, 2] = 1.0
+    b = li.gaussian_field(dims, 2042)
+    g = wd.wd_gauge_create(_t(unit), antiperiodic=False)
+    bd = _t(b)
+    for p in (wd.params(max_iter=60), wd.params(max_iter=60, mixed=False), wd.params(max_iter=60, defect_correction=True),
+              wd.params(max_iter=60, mixed=False, eo=False)):
+        x, st = wd.bicgstab_solve(g, 0.125, bd, p=p, raise_on_fail=False)
+        res = oracle.true_residual(unit, 0.125, _n(x), b, antiperiodic=False)
+        _say("zero mode", st, "oracle residual", res)
+        assert st["status"] in (wd._lib.WD_ERR_NOCONV, wd._lib.WD_ERR_BREAKDOWN), st
+        assert st["iters"] >= 1 and np.isfinite(st["true_rel_res"]) and st["true_rel_res"] > 1e-3, st
+        # the iterate grows along the null space, which M does not see: the residual an even-odd
+        # solve reports (from its last FP64 even-site residual and the reconstructed odd half)
+        # then carries rounding of order 1e-16 |x|, far above 1e-16 |b|
+        assert abs(st["true_rel_res"] - res) < 0.05 * res
+    xs, sts = wd.bicgstab_m_solve(g, [0.12, 0.125], bd, p=wd.params(mixed=False, eo=False, max_iter=60),
+                                  raise_on_fail=False)
+    _say("zero mode, BiCGstab-M", sts)
+    assert all(s["status"] in (wd._lib.WD_ERR_NOCONV, wd._lib.WD_ERR_BREAKDOWN) for s in sts), sts
+    g.close()
+
+
 def test_non_su3_links_use_the_exact_fp64_operator():
     """Links that are not SU(3) cannot be rebuilt from two rows: the FP64 solve must then use all 18
     reals (parity with the oracle on the same non-unitary field), and mixed precision with 12-real
@@ -546,7 +618,10 @@ def test_random_configurations_mixed(seed):
     x, st = wd.bicgstab_solve(g, c["kappa"], _t(b), p=wd.params(tol=1e-8, spinor=c["spinor"], links=c["links"],
                                                                delta=1e-2, defect_correction=c["dc"]))
     res = oracle.true_residual(U, c["kappa"], _n(x), b, antiperiodic=c["anti"])
+    _, n_ref, _, _ = oracle.bicgstab_eo(U, c["kappa"], b, tol=1e-8, antiperiodic=c["anti"])
+    _say("random case", seed, st, "oracle residual", res, "oracle FP64 iterations", n_ref)
     assert st["status"] == 0 and res < 1e-8, (c, st, res)
+    assert st["iters"] <= mixed_iteration_bound(n_ref, st["reliable_updates"]), (c, st, n_ref)
     g.close()
 
 
