@@ -139,6 +139,19 @@ wd_status wd_apply(wd_gauge* g, double kappa, double* out, const double* in, voi
 wd_status wd_apply_dag(wd_gauge* g, double kappa, double* out, const double* in, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): out = M(kappa) in (dagger = 0) or M(kappa)^dag in
+ * (dagger = 1), bitwise the result of wd_apply / wd_apply_dag, with no device or pinned
+ * allocation, no host-to-device copy and no synchronisation. The packed fields and the job table
+ * live in a fixed device array of 64 MiB per GPU that the library holds until the process ends;
+ * it fits lattices of at most 87,296 sites per parity after rounding V/2 up to a multiple of 256
+ * (16^3 x 32 fits, 24^4 does not); larger lattices give WD_ERR_ARG. Every call on one GPU uses
+ * that GPU's array: calls that overlap on one GPU (other streams or threads) race, so serialise
+ * them. in, out: device [V][3][4] complex128, distinct. Asynchronous on `stream`.
+ */
+wd_status wd_apply_noalloc(wd_gauge* g, double kappa, double* out, const double* in, int dagger, void* stream);
+
+/*
  * Single-mass BiCGstab for M(kappa) x = b (van der Vorst's method, cited in Sec. 6; the solution
  * update x <- x - beta s + chi w of Sec. 5). With params->eo the even-odd system of Sec. 6.2.3
  * (eq. eo2-eo4) is solved and the odd half rebuilt from eq. eo3. With params->mixed the

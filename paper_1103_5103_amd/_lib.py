@@ -87,7 +87,7 @@ EXPORTED = [
     "wd_params_default", "wd_gauge_create", "wd_gauge_destroy", "wd_apply", "wd_apply_dag", "bicgstab_solve",
     "bicgstab_m_solve", "wd_multimass_solve", "wd_batch_solve", "wd_normal_solve", "wd_gauge_grad",
     "wd_status_str", "wd_last_error", "wd_timing_enable", "wd_timing_reset", "wd_timing_get", "wd_gauge_device_bytes",
-    "wd_set_graphs", "wd_op_variant_default", "wd_apply_prec",
+    "wd_set_graphs", "wd_op_variant_default", "wd_apply_prec", "wd_apply_noalloc",
 ]
 
 _lib = None
@@ -114,6 +114,7 @@ def load(path: str = LIBPATH):
     L.wd_gauge_destroy.argtypes = [vp]
     for f in (L.wd_apply, L.wd_apply_dag):
         f.argtypes = [vp, d, vp, vp, vp]
+    L.wd_apply_noalloc.argtypes = [vp, d, vp, vp, i, vp]
     L.bicgstab_solve.argtypes = [vp, d, vp, vp, ctypes.POINTER(SolverParams), ctypes.POINTER(SolverStats), vp]
     L.bicgstab_m_solve.argtypes = [vp, i, ctypes.POINTER(d), ctypes.POINTER(vp), vp, ctypes.POINTER(SolverParams),
                                    ctypes.POINTER(SolverStats), vp]
@@ -142,7 +143,7 @@ def load(path: str = LIBPATH):
     L.wd_gauge_device_bytes.restype = ctypes.c_size_t
     for name in ("wd_gauge_create", "wd_gauge_destroy", "wd_apply", "wd_apply_dag", "bicgstab_solve",
                  "bicgstab_m_solve", "wd_multimass_solve", "wd_batch_solve", "wd_normal_solve", "wd_gauge_grad",
-                 "wd_last_error", "wd_timing_get", "wd_apply_prec"):
+                 "wd_last_error", "wd_timing_get", "wd_apply_prec", "wd_apply_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -286,6 +287,14 @@ def wd_apply_prec(g: Gauge, kappa: float, psi: torch.Tensor, p: SolverParams | N
     _check(load().wd_apply_prec(g.handle, float(kappa), _ptr(out, "out"), _ptr(psi, "in"), ctypes.byref(p),
                                 ctypes.byref(v), dots, _stream()))
     return out, np.array(dots[:], dtype=np.float64).reshape(v.copies, 3)
+
+
+def wd_apply_noalloc(g: Gauge, kappa: float, psi: torch.Tensor, out: torch.Tensor, dagger: bool = False) -> torch.Tensor:
+    """out = M(kappa) psi (or M^dag psi) with no device allocation by the library; out must be
+    given (a caller that cannot allocate owns it)."""
+    _check(load().wd_apply_noalloc(g.handle, float(kappa), _ptr(out, "out", g.field_shape),
+                                   _ptr(psi, "in", g.field_shape), int(bool(dagger)), _stream()))
+    return out
 
 
 NONFATAL = (WD_OK, WD_ERR_NOCONV, WD_ERR_BREAKDOWN, WD_ERR_NAN)

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwdirac.so")
-SOURCES = ["wd_hop_lo.hip", "wd_mrhs.hip", "wd_hop64.hip", "wd_kernels.hip", "wd_runtime.cpp", "wd_solve.cpp", "wd_api.cpp"]
+SOURCES = ["wd_hop_lo.hip", "wd_mrhs.hip", "wd_hop64.hip", "wd_kernels.hip", "wd_runtime.cpp", "wd_solve.cpp", "wd_api.cpp", "wd_noalloc.cpp"]
 ARCH = os.environ.get("WD_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -241,6 +241,19 @@ wd_status wd_apply_dag(wd_gauge* g, double kappa, double* out, const double* in,
     return apply_impl(g, kappa, out, in, stream, true);
 }
 
+wd_status wd_apply_noalloc(wd_gauge* g, double kappa, double* out, const double* in, int dagger, void* stream)
+{
+    return guarded([&]() -> wd_status {
+        if (!g) throw Error{WD_ERR_ARG, "NULL gauge"};
+        require_ptr(out, "out");
+        require_ptr(in, "in");
+        if (out == in) throw Error{WD_ERR_ARG, "in and out must be distinct"};
+        if (!(kappa > 0)) throw Error{WD_ERR_ARG, "kappa must be positive"};
+        apply_noalloc(g, kappa, out, in, dagger != 0, (hipStream_t)stream);
+        return WD_OK;
+    });
+}
+
 wd_status bicgstab_solve(wd_gauge* g, double kappa, double* x, const double* b, const wd_solver_params* params,
                          wd_solver_stats* stats, void* stream)
 {

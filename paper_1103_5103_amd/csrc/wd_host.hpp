@@ -156,6 +156,14 @@ void* pinned(size_t bytes);
 // handed out again after the device has drained (the ring synchronises when it wraps)
 char* stage_alloc(size_t bytes);
 
+// wd_apply_noalloc: a fixed device array per GPU (kNoallocScratchBytes) holds the job table and a
+// system record in its first kNoallocTableBytes, then the packed FP64 input and output fields
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+constexpr size_t kNoallocTableBytes = (size_t)64 << 10;
+constexpr int kNoallocMaxDevices = 64;
+size_t noalloc_scratch_need(long stride);
+void apply_noalloc(wd_gauge* g, double kappa, double* out, const double* in, bool dag, hipStream_t s);
+
 // launch helpers with optional timing
 // stage / ntl: -1 the defaults (LDS staging as built; non-temporal link loads unless the launch's
 // links are shared or small), else forced (0 off, 1 on)
