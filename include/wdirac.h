@@ -94,6 +94,13 @@ typedef struct {
                               links, then the unit matrix except on the last time slice, are neither
                               loaded nor multiplied. Only for links that are SU(3) to rounding (else
                               ignored). Solutions agree with the caller's gauge to rounding.          */
+    int gamma_basis;       /* read by wd_gauge_create only: 0 = the solvers work in the chiral basis of
+                              Sec. 2 (Table 1); 1 = in a non-chiral basis where gamma_4 is diagonal
+                              (a bandwidth saving named in Sec. 4): sources are rotated into it by
+                              psi S, S = [[1, 1], [-1, 1]] / sqrt(2) in 2x2 spin blocks, solutions
+                              back by S^dag, and a time hop reads two of the neighbour's four spin
+                              components. Fields crossing the ABI stay in the chiral basis; solutions
+                              agree with the chiral solves to rounding.                                */
 } wd_solver_params;
 
 typedef struct {
@@ -119,7 +126,7 @@ enum { WD_MIXED_RELIABLE = 0, WD_MIXED_DEFECT = 1 };
 
 /* Defaults: tol 1e-8, max_iter 5000, mixed 1, F32 spinors, F16 links, recon 12, eo 1,
    delta_reliable 0.1, use_x0 0, dagger 0, mixed_mode WD_MIXED_RELIABLE, guess_order 0,
-   temporal_gauge 0. */
+   temporal_gauge 0, gamma_basis 0. */
 void wd_params_default(wd_solver_params* p);
 
 /*

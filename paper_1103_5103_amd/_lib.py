@@ -46,6 +46,7 @@ class SolverParams(ctypes.Structure):
         ("mixed_mode", ctypes.c_int),
         ("guess_order", ctypes.c_int),
         ("temporal_gauge", ctypes.c_int),
+        ("gamma_basis", ctypes.c_int),
     ]
 
 
@@ -182,7 +183,7 @@ def _ptr(t: torch.Tensor, name: str, shape=None):
 
 def params(tol=1e-8, max_iter=5000, mixed=True, spinor="f32", links="f16", recon=12, eo=True, delta=0.1,
            use_x0=False, dagger=False, defect_correction=False, guess_order=0,
-           temporal_gauge=False) -> SolverParams:
+           temporal_gauge=False, nonchiral=False) -> SolverParams:
     p = SolverParams()
     load().wd_params_default(ctypes.byref(p))
     p.tol, p.max_iter, p.mixed = float(tol), int(max_iter), int(bool(mixed))
@@ -191,6 +192,7 @@ def params(tol=1e-8, max_iter=5000, mixed=True, spinor="f32", links="f16", recon
     p.mixed_mode = WD_MIXED_DEFECT if defect_correction else WD_MIXED_RELIABLE
     p.guess_order = int(guess_order)
     p.temporal_gauge = int(bool(temporal_gauge))
+    p.gamma_basis = int(bool(nonchiral))
     return p
 
 

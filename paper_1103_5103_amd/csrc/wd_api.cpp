@@ -164,6 +164,9 @@ wd_status wd_gauge_create(wd_gauge** out, const wd_geom* geom, const double* U, 
                 else g->ensure_links(L64_12, s);
             }
         }
+        if (hint && hint->gamma_basis != 0 && hint->gamma_basis != 1)
+            throw Error{WD_ERR_ARG, "gamma_basis must be 0 (chiral) or 1 (non-chiral)"};
+        g->nc = hint && hint->gamma_basis == 1 ? 1 : 0;
         if (hint && hint->mixed) g->ensure_slinks(link_fmt_of(hint->link_store, hint->recon), s);
         WD_CHECK_HIP(hipStreamSynchronize(s));
         *out = g.release();

@@ -66,6 +66,9 @@ template <class T> __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b)
 }
 template <class T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
 template <class T> __device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
+// fused multiply-add in the precision of T
+__device__ __forceinline__ float fmaf_t(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmaf_t(double a, double b, double c) { return fma(a, b, c); }
 // conj(a) * b
 template <class T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b)
 {

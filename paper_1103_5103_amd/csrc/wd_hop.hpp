@@ -64,6 +64,7 @@ struct HopIn {
     const Stg<SF, STG>& L;
     int base, nsl;
     bool tg;  // temporal gauge: unit time links inside the lattice
+    bool nc;  // spinors in the non-chiral basis (the time hop of hop_t_nc)
 };
 
 template <int MU, int D, bool DAG, int SFI, bool STG, class T>
@@ -143,6 +144,74 @@ __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int 
 
 // Directions whose loads may be scheduled together (2: the two of one axis). Larger groups let the
 // compiler issue more loads at once but spill registers (FP64) or lose occupancy.
+// Spin components s0, s0 + 1 of the three colours of input site i: h[a][c] = psi[c * 4 + s0 + a]
+// (two of the four spin components: half the bytes of a full spinor). FP16: the stored values
+// and the site's scale, returned separately (applied in the accumulation).
+template <int SF, int S0, class T>
+__device__ __forceinline__ T load_spin_pair(const SpinorRef& r, long i, cx<T> h[2][3])
+{
+    if constexpr (SF == SF64) {
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+#pragma unroll
+            for (int a = 0; a < 2; a++) {
+                const d2v q = gld<d2v>(r.p, chunk_at(12, r.cs, i, c * 4 + S0 + a));
+                h[a][c] = mk<T>((T)q[0], (T)q[1]);
+            }
+        return T(1);
+    } else if constexpr (SF == SF32) {
+        // chunk 2c + S0/2 holds spins S0, S0 + 1 of colour c
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const f4v q = gld<f4v>(r.p, chunk_at(6, r.cs, i, 2 * c + S0 / 2));
+            h[0][c] = mk<T>((T)q[0], (T)q[1]);
+            h[1][c] = mk<T>((T)q[2], (T)q[3]);
+        }
+        return T(1);
+    } else {
+        // chunk c holds the four spins of colour c (8 halves): read the 8 bytes of spins S0, S0 + 1
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const h4 q = gld<h4>(r.p, 2 * chunk_at(3, r.cs, i, c) + S0 / 2);
+            h[0][c] = mk<T>((T)(float)q[0], (T)(float)q[1]);
+            h[1][c] = mk<T>((T)(float)q[2], (T)(float)q[3]);
+        }
+        return (T)gld<float>(r.nrm, i);
+    }
+}
+
+// The time hop in the non-chiral basis, where gamma_4 = diag(1, 1, -1, -1): 1 - gamma_4 =
+// 2 diag(0, 0, 1, 1) and 1 + gamma_4 = 2 diag(1, 1, 0, 0), so the hop reads two of the neighbour's
+// spin components (S0 = 2 for the projector 1 - gamma_4, 0 for 1 + gamma_4), multiplies them by the
+// link and adds twice the product to the same two components of the output: no projection sums,
+// half the expansion, half the neighbour bytes of the chiral time hop.
+template <int D, bool DAG, int SFI, class T>
+__device__ __forceinline__ void hop_t_nc(const Geo& g, int x, int y, int z, int t, const SpinorRef& in,
+                                         const cx<T> W[9], cx<T> acc[12], int dep, bool unit)
+{
+    constexpr bool minus = (D == 0) != DAG;  // projector 1 - gamma_4
+    constexpr int S0 = minus ? 2 : 0;
+    const int nb = nb_index<3, D>(g, x, y, z, t) + dep;
+    cx<T> h[2][3];
+    const T sc = load_spin_pair<SFI, S0, T>(in, nb, h);
+    cx<T> gg[2][3];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+            gg[a][c] = unit ? h[a][c] : W[c * 3] * h[a][0] + W[c * 3 + 1] * h[a][1] + W[c * 3 + 2] * h[a][2];
+    // twice the product, with the boundary sign and (FP16 input) the site's scale
+    const bool flip = g.anti && (D == 0 ? (t == g.T - 1) : (t == 0));
+    const T f = (flip ? T(-2) : T(2)) * sc;
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            cx<T>& o = acc[c * 4 + S0 + a];
+            o = {fmaf_t(f, gg[a][c].re, o.re), fmaf_t(f, gg[a][c].im, o.im)};
+        }
+}
+
 template <int SF> struct HopGroup { static constexpr int G = 2; };
 
 // Between groups of directions: an empty asm that reads every accumulator and then "writes"
@@ -178,6 +247,13 @@ __device__ __forceinline__ void hop_axis(const Geo& g, int cb, int x, int y, int
     const bool unit_b = MU == 3 && in.tg && t != 0;
     if (!(unit_f && unit_b)) {
         load_link_pair<LF, T, NTL>(links, lcs, MU, cb + dep, Wf, Wb);
+    }
+    if (MU == 3 && in.nc) {
+        hop_t_nc<0, DAG, SFI, T>(g, x, y, z, t, in.in, Wf, acc, dep, unit_f);
+        group_barrier<2 * MU, G>(acc, dep);
+        hop_t_nc<1, DAG, SFI, T>(g, x, y, z, t, in.in, Wb, acc, dep, unit_b);
+        group_barrier<2 * MU + 1, G>(acc, dep);
+        return;
     }
     hop_dir<MU, 0, DAG, SFI, STG, T>(g, cb, x, y, z, t, in, Wf, acc, dep, unit_f);
     group_barrier<2 * MU, G>(acc, dep);
@@ -252,7 +328,7 @@ __global__ __launch_bounds__(BLOCK) void k_hop(
         }
         __syncthreads();
     }
-    const HopIn<SF, STG> hin{J.in, stg, base, nsl, TG && J.tg != 0};
+    const HopIn<SF, STG> hin{J.in, stg, base, nsl, TG && J.tg != 0, J.nc != 0};
     double v[NRED] = {0.0, 0.0, 0.0, 0.0};
     if (cb < J.g.Vh) {
         cx<T> acc[12];

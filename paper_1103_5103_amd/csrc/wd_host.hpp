@@ -125,6 +125,11 @@ struct wd_gauge {
     // built from the transformed links (links[] keeps the caller's gauge for wd_apply and the
     // gradient).
     bool tg = false;
+    // Solvers work in the non-chiral spin basis (gamma_4 diagonal) when the handle was created with
+    // that option: sources are rotated on the way in, solutions on the way out, and the hops take
+    // the time direction in that basis (half-spinor neighbours). wd_apply, wd_apply_noalloc and the
+    // gradient use the caller's basis.
+    int nc = 0;
     std::unique_ptr<wd::DevMem> gmat;                   // g(n), canonical [V][3][3] complex128
     std::unique_ptr<wd::DevMem> fixed[wd::NLINKFMT];    // transformed links, same layouts
     const double* gm() const { return tg ? (const double*)gmat->p : nullptr; }

@@ -607,13 +607,44 @@ __global__ __launch_bounds__(BLOCK) void k_dots_finish(const double* __restrict_
 
 // ================================================================ packing
 
+// Spin basis of the solvers' internal fields on a non-chiral handle: psi' = psi S with
+// S = (1/sqrt 2) [[1, 0, 1, 0], [0, 1, 0, 1], [-1, 0, 1, 0], [0, -1, 0, 1]] (spin index, fields
+// multiplied from the right as in eq. 4), for which S^dag gamma_4 S = diag(1, 1, -1, -1) while the
+// spatial gamma matrices of Sec. 2 are unchanged. Site values v[c * 4 + s].
+__device__ __forceinline__ void spin_to_nc(cx<double> v[12])
+{
+    const double r = 0.70710678118654752440;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const cx<double> a0 = v[c * 4], a1 = v[c * 4 + 1], a2 = v[c * 4 + 2], a3 = v[c * 4 + 3];
+        v[c * 4] = r * (a0 - a2);
+        v[c * 4 + 1] = r * (a1 - a3);
+        v[c * 4 + 2] = r * (a0 + a2);
+        v[c * 4 + 3] = r * (a1 + a3);
+    }
+}
+// psi = psi' S^dag
+__device__ __forceinline__ void spin_from_nc(cx<double> v[12])
+{
+    const double r = 0.70710678118654752440;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const cx<double> a0 = v[c * 4], a1 = v[c * 4 + 1], a2 = v[c * 4 + 2], a3 = v[c * 4 + 3];
+        v[c * 4] = r * (a0 + a2);
+        v[c * 4 + 1] = r * (a1 + a3);
+        v[c * 4 + 2] = r * (a2 - a0);
+        v[c * 4 + 3] = r * (a3 - a1);
+    }
+}
+
 // canonical [V][3][4] complex128 (lexicographic) <-> internal per-parity half fields.
 // gamma5 != 0 multiplies spin components 2 and 3 by -1 on the way (gamma5 = diag(1,1,-1,-1)).
 template <int SF>
 // gm (may be NULL): colour rotation g(n) applied on the way, psi'(n) = g(n) psi(n) (temporal gauge)
+// nc: then into the non-chiral basis (spin_to_nc)
 __global__ __launch_bounds__(BLOCK) void k_pack_spinor(const double2* __restrict__ src, Geo g, SpinorRef even,
                                                        SpinorRef odd, int gamma5, double scale,
-                                                       const double2* __restrict__ gm)
+                                                       const double2* __restrict__ gm, int nc)
 {
     const int p = blockIdx.y;
     const int cb = blockIdx.x * BLOCK + threadIdx.x;
@@ -640,14 +671,16 @@ __global__ __launch_bounds__(BLOCK) void k_pack_spinor(const double2* __restrict
 #pragma unroll
         for (int k = 0; k < 12; k++) v[k] = w[k];
     }
+    if (nc) spin_to_nc(v);
     store_spinor<SF, double>(p ? odd : even, cb, v);
 }
 
 template <int SF>
 // gm (may be NULL): psi(n) = g(n)^dag psi'(n) (back from temporal gauge)
+// nc: out of the non-chiral basis first (spin_from_nc)
 __global__ __launch_bounds__(BLOCK) void k_unpack_spinor(double2* __restrict__ dst, Geo g, SpinorRef even,
                                                          SpinorRef odd, int gamma5, double scale,
-                                                         const double2* __restrict__ gm)
+                                                         const double2* __restrict__ gm, int nc)
 {
     const int p = blockIdx.y;
     const int cb = blockIdx.x * BLOCK + threadIdx.x;
@@ -661,6 +694,7 @@ __global__ __launch_bounds__(BLOCK) void k_unpack_spinor(double2* __restrict__ d
     cx<double> w[12];
 #pragma unroll
     for (int k = 0; k < 12; k++) w[k] = mk<double>((double)v[k].re, (double)v[k].im);
+    if (nc) spin_from_nc(w);
     if (gm) {
         cx<double> G[9], u[12];
 #pragma unroll
@@ -686,7 +720,7 @@ __global__ __launch_bounds__(BLOCK) void k_unpack_spinor(double2* __restrict__ d
 // when xo.p is set), then the colour rotation, gamma5 and scale of k_unpack_spinor. FP64 fields.
 __global__ __launch_bounds__(BLOCK) void k_unpack_eo(double2* __restrict__ dst, Geo g, SpinorRef xe, SpinorRef xo,
                                                      SpinorRef bo, SpinorRef T, double c0, double c1, int gamma5,
-                                                     double scale, const double2* __restrict__ gm)
+                                                     double scale, const double2* __restrict__ gm, int nc)
 {
     const long n = (long)blockIdx.x * BLOCK + threadIdx.x;
     const long V = (long)g.X * g.Y * g.Z * g.T;
@@ -709,6 +743,7 @@ __global__ __launch_bounds__(BLOCK) void k_unpack_eo(double2* __restrict__ dst, 
         for (int k = 0; k < 12; k++) w[k] = c0 * w[k] + c1 * q[k];
         if (xo.p) store_spinor<SF64, double>(xo, cb, w);
     }
+    if (nc) spin_from_nc(w);
     if (gm) {
         cx<double> G[9], u[12];
 #pragma unroll
@@ -1064,24 +1099,24 @@ hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long n
 }
 
 hipError_t launch_pack_spinor(int sf, const double* src, const Geo& g, SpinorRef even, SpinorRef odd, int gamma5,
-                              double scale, hipStream_t s, const double* gm)
+                              double scale, hipStream_t s, const double* gm, int nc)
 {
     dim3 grid((unsigned)((g.Vh + BLOCK - 1) / BLOCK), 2);
     const double2* G = (const double2*)gm;
-    if (sf == SF64) hipLaunchKernelGGL((k_pack_spinor<SF64>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale, G);
-    else if (sf == SF32) hipLaunchKernelGGL((k_pack_spinor<SF32>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale, G);
-    else hipLaunchKernelGGL((k_pack_spinor<SF16>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale, G);
+    if (sf == SF64) hipLaunchKernelGGL((k_pack_spinor<SF64>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale, G, nc);
+    else if (sf == SF32) hipLaunchKernelGGL((k_pack_spinor<SF32>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale, G, nc);
+    else hipLaunchKernelGGL((k_pack_spinor<SF16>), grid, dim3(BLOCK), 0, s, (const double2*)src, g, even, odd, gamma5, scale, G, nc);
     return hipGetLastError();
 }
 
 hipError_t launch_unpack_spinor(int sf, double* dst, const Geo& g, SpinorRef even, SpinorRef odd, int gamma5,
-                                double scale, hipStream_t s, const double* gm)
+                                double scale, hipStream_t s, const double* gm, int nc)
 {
     dim3 grid((unsigned)((g.Vh + BLOCK - 1) / BLOCK), 2);
     const double2* G = (const double2*)gm;
-    if (sf == SF64) hipLaunchKernelGGL((k_unpack_spinor<SF64>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale, G);
-    else if (sf == SF32) hipLaunchKernelGGL((k_unpack_spinor<SF32>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale, G);
-    else hipLaunchKernelGGL((k_unpack_spinor<SF16>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale, G);
+    if (sf == SF64) hipLaunchKernelGGL((k_unpack_spinor<SF64>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale, G, nc);
+    else if (sf == SF32) hipLaunchKernelGGL((k_unpack_spinor<SF32>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale, G, nc);
+    else hipLaunchKernelGGL((k_unpack_spinor<SF16>), grid, dim3(BLOCK), 0, s, (double2*)dst, g, even, odd, gamma5, scale, G, nc);
     return hipGetLastError();
 }
 
@@ -1141,11 +1176,11 @@ hipError_t launch_dots(SpinorRef a, const SpinorRef* bs, int m, const Geo& g, do
 }
 
 hipError_t launch_unpack_eo(double* dst, const Geo& g, SpinorRef xe, SpinorRef xo, SpinorRef bo, SpinorRef T,
-                            double c0, double c1, int gamma5, double scale, hipStream_t s, const double* gm)
+                            double c0, double c1, int gamma5, double scale, hipStream_t s, const double* gm, int nc)
 {
     const long V = (long)g.X * g.Y * g.Z * g.T;
     hipLaunchKernelGGL(k_unpack_eo, grid1((V + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, (double2*)dst, g, xe, xo, bo, T,
-                       c0, c1, gamma5, scale, (const double2*)gm);
+                       c0, c1, gamma5, scale, (const double2*)gm, nc);
     return hipGetLastError();
 }
 

@@ -26,16 +26,18 @@ hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState
 hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long nblocks, SysState* sys, int gated,
                         hipStream_t s, int* exec = nullptr);
 // gm (may be NULL): canonical [V][3][3] colour rotation g(n): pack stores g(n) psi(n), unpack
-// returns g(n)^dag psi'(n)
+// returns g(n)^dag psi'(n). nc: the internal field is in the non-chiral spin basis (pack rotates
+// into it after gamma5 and g(n), unpack out of it before them)
 hipError_t launch_pack_spinor(int sf, const double* src, const Geo& g, SpinorRef even, SpinorRef odd, int gamma5,
-                              double scale, hipStream_t s, const double* gm = nullptr);
+                              double scale, hipStream_t s, const double* gm = nullptr, int nc = 0);
 hipError_t launch_unpack_spinor(int sf, double* dst, const Geo& g, SpinorRef even, SpinorRef odd, int gamma5,
-                                double scale, hipStream_t s, const double* gm = nullptr);
+                                double scale, hipStream_t s, const double* gm = nullptr, int nc = 0);
 hipError_t launch_pack_links(const double* U, const Geo& g, void* even, void* odd, long lcs, hipStream_t s);
 // canonical output of an even-odd solve: even sites from xe, odd sites c0 bo + c1 T (eq. eo3 with
 // T = D_oe x_e), also stored into xo when xo.p is set; FP64 views of one parity each
 hipError_t launch_unpack_eo(double* dst, const Geo& g, SpinorRef xe, SpinorRef xo, SpinorRef bo, SpinorRef T,
-                            double c0, double c1, int gamma5, double scale, hipStream_t s, const double* gm = nullptr);
+                            double c0, double c1, int gamma5, double scale, hipStream_t s, const double* gm = nullptr,
+                            int nc = 0);
 // internal links of format src_lf (L64_18 or L64_12) -> format lf, both output parities' halves
 // separately (called per half)
 hipError_t launch_convert_links(int lf, int src_lf, const void* src, void* dst, int Vh, long lcs, hipStream_t s);

@@ -44,10 +44,16 @@ __device__ __forceinline__ void mrhs_axis(const HopJob* __restrict__ jobs, int j
     const bool unit_b = MU == 3 && tg && t != 0;
     cx<T> Wf[9], Wb[9];
     if (!(unit_f && unit_b)) load_link_pair<LF, T, true>(J0.links, J0.lcs, MU, cb + dep, Wf, Wb);
+    const bool nc = MU == 3 && J0.nc != 0;  // the systems of a group share one handle, hence its basis
 #pragma unroll
     for (int k = 0; k < KT; k++)
         if (run[k]) {
-            const HopIn<SF, true> in{jobs[j0 + k].in, stg[k], base, nsl, tg};
+            if (nc) {
+                hop_t_nc<0, DAG, SF, T>(g, x, y, z, t, jobs[j0 + k].in, Wf, acc[k], dep, unit_f);
+                hop_t_nc<1, DAG, SF, T>(g, x, y, z, t, jobs[j0 + k].in, Wb, acc[k], dep, unit_b);
+                continue;
+            }
+            const HopIn<SF, true> in{jobs[j0 + k].in, stg[k], base, nsl, tg, false};
             hop_dir<MU, 0, DAG, SF, true, T>(g, cb, x, y, z, t, in, Wf, acc[k], dep, unit_f);
             hop_dir<MU, 1, DAG, SF, true, T>(g, cb, x, y, z, t, in, Wb, acc[k], dep, unit_b);
         }

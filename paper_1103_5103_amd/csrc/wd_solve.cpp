@@ -256,6 +256,7 @@ HopChoice tune_hop(wd_gauge* g, int sf, int lf, hipStream_t st, int nshared)
         for (int k = 0; k < nc; k++) {
             HopJob j = hop_job(G, 1, k, in[k].all(), out[k].all(), g->slk(lf, 1), g->lcs(), 1.0);
             j.tg = g->tg;
+            j.nc = g->nc;
             j.rhs = cands[c].rhs;
             set_tile(j, cands[c].tz);
             tabs[c].host.push_back(j);
@@ -489,7 +490,7 @@ static void prepare_source(wd_gauge* g, const std::string& key, const double* b,
 {
     src.B64 = g->field(key + "B64", SF64, 2);
     src.HB = g->field(key + "HB", SF64, 1);
-    WD_CHECK_HIP(launch_pack_spinor(SF64, b, g->geo, src.B64.half(0), src.B64.half(1), dagger, 1.0, st, g->gm()));
+    WD_CHECK_HIP(launch_pack_spinor(SF64, b, g->geo, src.B64.half(0), src.B64.half(1), dagger, 1.0, st, g->gm(), g->nc));
     src.bb = -1;
 }
 
@@ -660,7 +661,10 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
             j.rhs = rhs_lo;
         }
     for (auto* t : {&Hhb, &Hx1, &Hx2, &Hrec, &H1, &H2, &H3, &H4}) {
-        for (auto& j : t->host) j.tg = S[j.sys].g->tg;  // solver links of a temporal-gauge handle
+        for (auto& j : t->host) {
+            j.tg = S[j.sys].g->tg;  // solver links of a temporal-gauge handle
+            j.nc = S[j.sys].g->nc;  // and the handle's spin basis
+        }
         group_by_links(*t);
         layout(*t);
     }
@@ -686,7 +690,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         if (e.x_ready) continue;
         if (P.use_x0)
             WD_CHECK_HIP(launch_pack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0, st,
-                                            e.g->gm()));
+                                            e.g->gm(), e.g->nc));
         else
             WD_CHECK_HIP(hipMemsetAsync(e.X64.base(), 0, e.X64.mem->bytes, st));
     }
@@ -855,10 +859,10 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
             if (sys.h[i].status == ST_SEL1)  // x_o = (b_o + 1/2 T64) / a, rebuilt while unpacking
                 WD_CHECK_HIP(launch_unpack_eo(e.x, e.g->geo, e.X64.half(0), e.keep_odd ? e.X64.half(1) : SpinorRef{},
                                               e.src.B64.half(1), e.T64.all(), 1.0 / e.a, 0.5 / e.a, P.dagger, 1.0,
-                                              st, e.g->gm()));
+                                              st, e.g->gm(), e.g->nc));
             else
                 WD_CHECK_HIP(launch_unpack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), P.dagger, 1.0,
-                                                  st, e.g->gm()));
+                                                  st, e.g->gm(), e.g->nc));
         }
     }
     sys.download(st);
@@ -939,7 +943,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
     q.shv = d_shv;
     sys.upload(st);
 
-    WD_CHECK_HIP(launch_pack_spinor(SF64, b, geo, B.half(0), B.half(1), P.dagger, 1.0, st, g->gm()));
+    WD_CHECK_HIP(launch_pack_spinor(SF64, b, geo, B.half(0), B.half(1), P.dagger, 1.0, st, g->gm(), g->nc));
     const long nsites = B.nsites();
     JobTable<SweepJob> Init, SW, SXR, SEND;
     SweepJob j = sweep_job(0, nsites);
@@ -975,12 +979,14 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
     for (int p = 0; p < 2; p++) {
         HopJob h = hop_job(geo, p, 0, Sv.half(1 - p), AS.half(p), g->slk(L64, p), g->lcs(), -0.5);
         h.tg = g->tg;
+        h.nc = g->nc;
         h.x0 = Sv.half(p);
         h.c0 = a;
         h.z = B.half(p);
         HAs.host.push_back(h);
         h = hop_job(geo, p, 0, W.half(1 - p), AW.half(p), g->slk(L64, p), g->lcs(), -0.5);
         h.tg = g->tg;
+        h.nc = g->nc;
         h.x0 = W.half(p);
         h.c0 = a;
         HAw.host.push_back(h);
@@ -1072,6 +1078,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
             for (int p = 0; p < 2; p++) {
                 HopJob h = hop_job(geo, p, i, Xi.half(1 - p), RES.half(p), g->slk(L64, p), g->lcs(), 0.5);
                 h.tg = g->tg;
+                h.nc = g->nc;
                 h.x0 = B.half(p);
                 h.c0 = 1.0;
                 h.x1 = Xi.half(p);
@@ -1086,7 +1093,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
         run_hop(SF64, L64, false, RED_NORM, FIN_STORE, R, rs.d(), 0, st, 0);
         for (int i = 0; i < nk; i++) {
             const Field& Xi = i == base ? X : XS[shift_of[i]];
-            WD_CHECK_HIP(launch_unpack_spinor(SF64, x[i], geo, Xi.half(0), Xi.half(1), P.dagger, 1.0, st, g->gm()));
+            WD_CHECK_HIP(launch_unpack_spinor(SF64, x[i], geo, Xi.half(0), Xi.half(1), P.dagger, 1.0, st, g->gm(), g->nc));
         }
         rs.download(st);
         if (stats)
@@ -1223,11 +1230,13 @@ wd_status apply_prec(wd_gauge* g, double kappa, double* out, const double* in, c
     for (int k = 0; k < K; k++) {
         HopJob j = hop_job(G, 1, k, F[k].half(0), Tm[k].all(), g->slk(LFL, 1), g->lcs(), 1.0);
         j.tg = tg;
+        j.nc = g->nc;
         j.rhs = rhs;
         set_tile(j, tz);
         H1.host.push_back(j);
         j = hop_job(G, 0, k, Tm[k].all(), O[k].all(), g->slk(LFL, 0), g->lcs(), -0.25);
         j.tg = tg;
+        j.nc = g->nc;
         j.rhs = rhs;
         j.x0 = F[k].half(0);
         j.c0 = a * a;
@@ -1239,7 +1248,7 @@ wd_status apply_prec(wd_gauge* g, double kappa, double* out, const double* in, c
     layout(H2);
     upload_tables(st, g->raw["ap.tables"], {&H1, &H2});
     for (int k = 0; k < K; k++)
-        WD_CHECK_HIP(launch_pack_spinor(SFL, in + (size_t)k * V * 24, G, F[k].half(0), F[k].half(1), 0, 1.0, st, g->gm()));
+        WD_CHECK_HIP(launch_pack_spinor(SFL, in + (size_t)k * V * 24, G, F[k].half(0), F[k].half(1), 0, 1.0, st, g->gm(), g->nc));
     const int ext[4] = {1, 2, 1, 1};  // epilogue fields read by the second hop (x0, and z for ZDOT)
     run_hop(SFL, LFL, v.dagger != 0, RED_NONE, FIN_STORE, H1, sys.d(), 0, st, hop_bytes(H1, SFL, LFL, 0), v.stage,
             v.nontemporal);
@@ -1248,7 +1257,7 @@ wd_status apply_prec(wd_gauge* g, double kappa, double* out, const double* in, c
             v.stage, v.nontemporal);
     for (int k = 0; k < K; k++)
         WD_CHECK_HIP(
-            launch_unpack_spinor(SFL, out + (size_t)k * V * 24, G, O[k].all(), Tm[k].all(), 0, 1.0, st, g->gm()));
+            launch_unpack_spinor(SFL, out + (size_t)k * V * 24, G, O[k].all(), Tm[k].all(), 0, 1.0, st, g->gm(), g->nc));
     sys.download(st);
     if (dots)
         for (int k = 0; k < K; k++)
@@ -1738,6 +1747,7 @@ static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream
     for (auto* t : {&Hx1, &Hx2, &H1, &H2})
         for (auto& j : t->host) j.tg = S[j.sys].g->tg;
     for (auto* t : {&Hx1, &Hx2, &Hx3, &Hx4, &H1, &H2, &H3, &H4}) {
+        for (auto& j : t->host) j.nc = S[j.sys].g->nc;  // every hop works in the handle's spin basis
         group_by_links(*t);
         layout(*t);
     }
@@ -1902,7 +1912,7 @@ static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream
     }
 
     for (auto& e : S)
-        WD_CHECK_HIP(launch_unpack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), 0, 1.0, st, e.g->gm()));
+        WD_CHECK_HIP(launch_unpack_spinor(SF64, e.x, e.g->geo, e.X64.half(0), e.X64.half(1), 0, 1.0, st, e.g->gm(), e.g->nc));
     sys.download(st);
     for (int i = 0; i < n; i++) {
         CgSys& e = S[i];
@@ -1940,7 +1950,7 @@ static wd_status cgm_solve(wd_gauge* g, double kappa, int n, const double* sigma
     Field R = g->field("cgm.r", SF64, 1), Pb = g->field("cgm.p", SF64, 1), Tm = g->field("cgm.t", SF64, 1);
     Field Vm = g->field("cgm.v", SF64, 1), Wm = g->field("cgm.w", SF64, 1);
     for (int i = 0; i < n; i++) WD_CHECK_HIP(hipMemsetAsync(X[i].base(), 0, X[i].mem->bytes, st));
-    WD_CHECK_HIP(launch_pack_spinor(SF64, b, geo, B.half(0), B.half(1), 0, 1.0, st, g->gm()));
+    WD_CHECK_HIP(launch_pack_spinor(SF64, b, geo, B.half(0), B.half(1), 0, 1.0, st, g->gm(), g->nc));
 
     SysArray sys;
     sys.alloc(1, g->raw["cgm.sys"]);
@@ -2003,9 +2013,11 @@ static wd_status cgm_solve(wd_gauge* g, double kappa, int n, const double* sigma
         const long lcs = g->lcs();
         HopJob h = hop_job(geo, 1, 0, Pb.all(), Tm.all(), d1, lcs, 1.0);
         h.tg = g->tg;
+        h.nc = g->nc;
         H1.host.push_back(h);
         h = hop_job(geo, 0, 0, Tm.all(), Vm.all(), d0, lcs, -0.25);
         h.tg = g->tg;
+        h.nc = g->nc;
         h.x0 = Pb.all();
         h.c0 = a2;
         H2.host.push_back(h);
@@ -2020,7 +2032,10 @@ static wd_status cgm_solve(wd_gauge* g, double kappa, int n, const double* sigma
     }
     const int tz64 = tune_tile(g, SF64, L64, st);
     for (auto* t : {&H1, &H2, &H3, &H4}) {
-        for (auto& h : t->host) set_tile(h, tz64);
+        for (auto& h : t->host) {
+            set_tile(h, tz64);
+            h.nc = g->nc;  // the adjoint hops too work in the handle's spin basis
+        }
         layout(*t);
     }
     for (auto* t : {&Init, &SX, &SP}) layout(*t);
@@ -2115,9 +2130,11 @@ static wd_status cgm_solve(wd_gauge* g, double kappa, int n, const double* sigma
             Bs.host.push_back(sj);
             HopJob h = hop_job(geo, 1, i, X[i].half(0), RT[i].all(), d1, lcs, 1.0);
             h.tg = g->tg;
+            h.nc = g->nc;
             Q1.host.push_back(h);
             h = hop_job(geo, 0, i, RT[i].all(), RV[i].all(), d0, lcs, -0.25);
             h.tg = g->tg;
+            h.nc = g->nc;
             h.x0 = X[i].half(0);
             h.c0 = a2;
             Q2.host.push_back(h);
@@ -2130,7 +2147,10 @@ static wd_status cgm_solve(wd_gauge* g, double kappa, int n, const double* sigma
             Q4.host.push_back(h);
         }
         for (auto* t : {&Q1, &Q2, &Q3, &Q4}) {
-            for (auto& h : t->host) set_tile(h, tz64);
+            for (auto& h : t->host) {
+                set_tile(h, tz64);
+                h.nc = g->nc;
+            }
             layout(*t);
         }
         layout(Bs);
@@ -2142,7 +2162,7 @@ static wd_status cgm_solve(wd_gauge* g, double kappa, int n, const double* sigma
         run_hop(SF64, L64, true, RED_NONE, FIN_STORE, Q3, rs.d(), 0, st, 0);
         run_hop(SF64, L64, true, RED_NORM, FIN_STORE, Q4, rs.d(), 0, st, 0);
         for (int i = 0; i < n; i++)
-            WD_CHECK_HIP(launch_unpack_spinor(SF64, x[i], geo, X[i].half(0), X[i].half(1), 0, 1.0, st, g->gm()));
+            WD_CHECK_HIP(launch_unpack_spinor(SF64, x[i], geo, X[i].half(0), X[i].half(1), 0, 1.0, st, g->gm(), g->nc));
         rs.download(st);
         if (stats)
             for (int i = 0; i < n; i++) {

@@ -115,6 +115,8 @@ struct HopJob {
     // site applies the hop to all ilv (<= rhs) systems of the group, loading each link once; the
     // group then spans nblk blocks rather than ilv * nblk. Every job of a launch has the same mode.
     int rhs;
+    int nc;              // spinors in the non-chiral basis (gamma_4 diagonal): time hops read and
+                         // update two spin components (hop_t_nc)
 };
 
 // Roles of the fields of a sweep job

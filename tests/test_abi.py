@@ -46,6 +46,7 @@ def test_binding_loads_and_defaults():
     assert wd.params(defect_correction=True).mixed_mode == wd.WD_MIXED_DEFECT
     assert p.guess_order == 0 and wd.params(guess_order=3).guess_order == 3
     assert p.temporal_gauge == 0 and wd.params(temporal_gauge=True).temporal_gauge == 1
+    assert p.gamma_basis == 0 and wd.params(nonchiral=True).gamma_basis == 1
     assert wd._lib.status_name(4) == "WD_ERR_NOCONV"
     v = wd.op_variant()
     assert (v.red, v.stage, v.nontemporal, v.tile, v.copies, v.rhs_per_thread, v.dagger) == (0, -1, -1, -1, 1, -1, 0)
@@ -63,13 +64,13 @@ def test_struct_layout_matches_c_compiler(tmp_path):
         '#include <stdio.h>\n#include <stddef.h>\n#include "wdirac.h"\n'
         "int main(void){"
         'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(wd_solver_params), offsetof(wd_solver_params, delta_reliable),'
-        " offsetof(wd_solver_params, dagger), offsetof(wd_solver_params, temporal_gauge), sizeof(wd_solver_stats),"
+        " offsetof(wd_solver_params, dagger), offsetof(wd_solver_params, gamma_basis), sizeof(wd_solver_stats),"
         " offsetof(wd_solver_stats, true_rel_res),"
         " sizeof(wd_system), sizeof(wd_geom), sizeof(wd_op_variant), offsetof(wd_op_variant, dagger)); return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(wd.SolverParams), wd.SolverParams.delta_reliable.offset, wd.SolverParams.dagger.offset,
-            wd.SolverParams.temporal_gauge.offset, ctypes.sizeof(wd.SolverStats), wd.SolverStats.true_rel_res.offset, ctypes.sizeof(wd._lib.System),
+            wd.SolverParams.gamma_basis.offset, ctypes.sizeof(wd.SolverStats), wd.SolverStats.true_rel_res.offset, ctypes.sizeof(wd._lib.System),
             ctypes.sizeof(wd._lib.Geom), ctypes.sizeof(wd.OpVariant), wd.OpVariant.dagger.offset]
     assert got == want

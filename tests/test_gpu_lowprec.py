@@ -305,3 +305,45 @@ def test_operator_argument_errors():
     ref, pe, odd = reference(U * 1.05, 0.1, _n(psi), False, True)
     check(_n(out), ref, odd, "f64", "non-SU(3) links, 18 reals")
     g.close()
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (6, 4, 4, 10), (8, 4, 4, 2), (16, 32, 4, 4)])
+@pytest.mark.parametrize("fmt", ["f64", "f32/f32", "f32/f16", "f16/f16", "f32/bf16", "f32/f16r8"])
+def test_operator_nonchiral_basis(dims, fmt):
+    """A handle in the non-chiral basis (gamma_4 diagonal: the time hops read two spin components
+    of each neighbour): every reduction, the adjoint hops, with and without LDS staging, against
+    the oracle's operator in the paper's chiral basis (the call rotates in and out)."""
+    U = li.random_links(dims, 1.0, 1800)
+    psi = li.gaussian_field(dims, 2800)
+    kappa = 0.127
+    g = wd.wd_gauge_create(_t(U), hint=wd.params(nonchiral=True))
+    p = wd.params(**FORMATS[fmt][0])
+    for dag, red in ((False, "zdot"), (False, "outx"), (False, "none"), (True, "none"), (True, "zdot")):
+        for stage in (0, 1):
+            out, dots = wd.wd_apply_prec(g, kappa, _t(psi), p=p, v=wd.op_variant(red=red, dagger=dag, stage=stage))
+            out = _n(out)
+            ref, pe, odd = reference(U, kappa, psi, dag, True)
+            check(out, ref, odd, fmt, f"non-chiral {dims} dag={dag} red={red} stage={stage}")
+            check_dots(dots[0], out, pe, odd, red, max(FORMATS[fmt][1], 1e-12))
+    g.close()
+
+
+@pytest.mark.parametrize("fmt", ["f32/f16", "f16/f16", "f32/f32"])
+def test_operator_nonchiral_multi_rhs_and_temporal_gauge(fmt):
+    """The non-chiral time hop inside the multi-RHS hop, and combined with the temporal gauge (unit
+    time links skipped on the interior slices)."""
+    dims = (16, 8, 8, 6)
+    U = li.random_links(dims, 1.0, 1810)
+    psis = np.stack([li.gaussian_field(dims, 2810 + k) for k in range(3)])
+    for tg in (False, True):
+        g = wd.wd_gauge_create(_t(U), hint=wd.params(nonchiral=True, temporal_gauge=tg))
+        for rhs in (0, 2, 4):
+            for dag, red in ((False, "outx"), (True, "zdot")):
+                out, dots = wd.wd_apply_prec(g, 0.125, _t(psis), p=wd.params(**FORMATS[fmt][0]),
+                                             v=wd.op_variant(red=red, copies=3, rhs_per_thread=rhs, dagger=dag))
+                out = _n(out)
+                for k in range(3):
+                    ref, pe, odd = reference(U, 0.125, psis[k], dag, True)
+                    check(out[k], ref, odd, fmt, f"non-chiral tg={tg} rhs={rhs} dag={dag} copy {k}")
+                    check_dots(dots[k], out[k], pe, odd, red, max(FORMATS[fmt][1], 1e-12))
+        g.close()
