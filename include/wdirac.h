@@ -299,7 +299,10 @@ wd_status wd_last_error(char* buf, size_t n);
  * brackets each launch of the named kernel classes with HIP events on the launch stream and
  * accumulates their durations; reading the totals synchronises the recorded events.
  * class: 0 = low-precision even-odd hop, 1 = FP64 hop, 2 = fused vector sweeps,
- *        3 = the small finisher kernels that complete the reductions.
+ *        3 = the small finisher kernels that complete the reductions, 4 + r = the low-precision
+ *        hops with fused reduction r (WD_RED_NONE .. WD_RED_NORM; also counted in class 0).
+ * bytes: the compulsory bytes of the counted launches (launches in which every system was gated
+ *        off are not counted).
  */
 void wd_timing_enable(int on);
 void wd_timing_reset(void);

@@ -406,7 +406,7 @@ void wd_timing_reset(void)
 wd_status wd_timing_get(int cls, double* total_ms, long* launches, double* bytes)
 {
     return guarded([&]() -> wd_status {
-        if (cls < 0 || cls >= NTK) throw Error{WD_ERR_ARG, "bad kernel class"};  // 3: finisher kernels
+        if (cls < 0 || cls >= NTK) throw Error{WD_ERR_ARG, "bad kernel class"};
         Timer& t = timer();
         t.flush();
         if (total_ms) *total_ms = t.ms[cls];

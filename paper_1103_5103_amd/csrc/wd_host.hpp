@@ -66,18 +66,20 @@ struct Field {
 size_t field_bytes(int sf, int halves, long stride);
 
 // ---------------------------------------------------------------- timing
-enum { TK_HOP_LO = 0, TK_HOP_F64 = 1, TK_SWEEP = 2, TK_FINISH = 3, NTK = 4 };
+// TK_HOP_LO_RED + r: the low-precision hops with fused reduction r (RED_NONE .. RED_NORM), also
+// counted in TK_HOP_LO
+enum { TK_HOP_LO = 0, TK_HOP_F64 = 1, TK_SWEEP = 2, TK_FINISH = 3, TK_HOP_LO_RED = 4, NTK = 8 };
 struct Timer {
     bool on = false;
-    struct Rec { int cls; hipEvent_t a, b; double bytes; int slot; int njobs; };
+    struct Rec { int cls; hipEvent_t a, b; double bytes; int slot; int njobs; int cls2; };
     std::vector<Rec> pending;
     std::vector<hipEvent_t> pool;
     int* dflags = nullptr;  // per pending launch: set by the kernel when it did work
     size_t cap = 0;
     int* slot();
-    double ms[NTK] = {0, 0, 0, 0};
-    double bytes[NTK] = {0, 0, 0, 0};
-    long launches[NTK] = {0, 0, 0, 0};
+    double ms[NTK] = {};
+    double bytes[NTK] = {};
+    long launches[NTK] = {};
     hipEvent_t get();
     void flush();
 };

@@ -126,6 +126,11 @@ void Timer::flush()
             const double frac = (r.slot < 0 || r.njobs <= 0) ? 1.0 : std::min(1.0, (double)done[k] / r.njobs);
             bytes[r.cls] += r.bytes * frac;
             launches[r.cls] += 1;
+            if (r.cls2 >= 0) {
+                ms[r.cls2] += t;
+                bytes[r.cls2] += r.bytes * frac;
+                launches[r.cls2] += 1;
+            }
         }
         pool.push_back(r.a);
         pool.push_back(r.b);
@@ -235,7 +240,7 @@ static void run_finish(int nr, int fin, const JobTable<J>& t, SysState* sys, int
     WD_CHECK_HIP(launch_finish(nr, fin, t.fin_d(), (int)t.fin.size(), sys, gated, s));
     if (T.on) {
         WD_CHECK_HIP(hipEventRecord(b, s));
-        T.pending.push_back({TK_FINISH, a, b, 0.0, -1, 0});
+        T.pending.push_back({TK_FINISH, a, b, 0.0, -1, 0, -1});
     }
 }
 
@@ -275,7 +280,7 @@ void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>&
     }
     if (T.on) {
         WD_CHECK_HIP(hipEventRecord(b, s));
-        T.pending.push_back({cls, a, b, bytes, (int)(flag - T.dflags), t.n()});
+        T.pending.push_back({cls, a, b, bytes, (int)(flag - T.dflags), t.n(), cls == TK_HOP_LO ? TK_HOP_LO_RED + red : -1});
     }
     if (red != RED_NONE) run_finish(3, fin, t, sys, gated, s);
 }
@@ -294,7 +299,7 @@ void run_sweep(int op, int sfl, const JobTable<SweepJob>& t, SysState* sys, int 
     WD_CHECK_HIP(launch_sweep(op, sfl, t.d(), t.n(), t.nblocks, sys, gated, s, flag));
     if (T.on) {
         WD_CHECK_HIP(hipEventRecord(b, s));
-        T.pending.push_back({TK_SWEEP, a, b, bytes, (int)(flag - T.dflags), t.n()});
+        T.pending.push_back({TK_SWEEP, a, b, bytes, (int)(flag - T.dflags), t.n(), -1});
     }
     switch (op) {
     case OP_XR: run_finish(3, FIN_ALPHA, t, sys, gated, s); break;

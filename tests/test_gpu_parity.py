@@ -627,13 +627,18 @@ def test_nonchiral_basis_solves_every_method(dims, anti):
 def test_graph_replays_match_eager_launches():
     """Each solve replays its captured iteration chunk many times, with eager reliable updates and
     host synchronisations in between; with deterministic reductions the result must be bitwise
-    equal to launching every kernel eagerly."""
+    equal to launching every kernel eagerly. Covers the single-mass, BiCGstab-M, sequential and
+    batched multi-mass solves and a batch over three lattices."""
     dims = (8, 8, 8, 16)
     U = li.random_links(dims, 1.0, 1070)
     b = li.gaussian_field(dims, 2070)
     g = wd.wd_gauge_create(_t(U))
     bd = _t(b)
     kappas = [0.124, 0.128, 0.132]
+    # a batch over uneven lattices (the batched workload's shape: systems sharing a gauge field
+    # run in one launch, here with the multi-RHS hop when the tuner picks it for FP16 spinors)
+    side = [((4, 4, 4, 4), 1071), ((6, 6, 6, 6), 1072)]
+    handles = [(wd.wd_gauge_create(_t(li.random_links(d, 1.0, sd))), d, sd) for d, sd in side]
     out = {}
     try:
         for mode in (True, False):
@@ -641,12 +646,23 @@ def test_graph_replays_match_eager_launches():
             x1, s1 = wd.bicgstab_solve(g, 0.13, bd, p=wd.params(tol=1e-9, spinor="f16", links="bf16", delta=0.1))
             xm, sm = wd.bicgstab_m_solve(g, kappas, bd, p=wd.params(tol=1e-10, mixed=False, eo=False))
             xs, ss = wd.wd_multimass_solve(g, kappas, bd)
-            out[mode] = [x1] + xm + xs
+            xb, sb = wd.wd_multimass_solve(g, kappas, bd, method=wd.WD_METHOD_BATCHED,
+                                           p=wd.params(tol=1e-9, spinor="f16", delta=0.05))
+            systems = [(g, k, bd, torch.zeros_like(bd)) for k in kappas]
+            for h, d, sd in handles:
+                bh = _t(li.gaussian_field(d, sd + 1000))
+                systems += [(h, k, bh, torch.zeros_like(bh)) for k in kappas]
+            sts = wd.wd_batch_solve(systems, p=wd.params(tol=1e-9, spinor="f16", delta=0.05))
+            out[mode] = [x1] + xm + xs + xb + [x for (_, _, _, x) in systems]
             assert s1["reliable_updates"] >= 2
+            assert all(s["status"] == 0 for s in sts + sb)
+            assert max(s["reliable_updates"] for s in sb) >= 2
     finally:
         wd.set_graphs(False)
     for a, c in zip(out[True], out[False]):
         assert torch.equal(a, c)
+    for h, _, _ in handles:
+        h.close()
     g.close()
 
 
