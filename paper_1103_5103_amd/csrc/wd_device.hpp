@@ -352,13 +352,51 @@ __device__ __forceinline__ unsigned short f32_to_bf16(float f)
 // so a hop reads both links of a direction with three 16-byte loads.
 __host__ __device__ constexpr bool link_paired(int f) { return f == L16_12 || f == LB16_12; }
 
+// conj(a b - c d) as two chains of fused multiply-adds (1 multiply + 3 FMAs per component, where
+// forming the two products first and subtracting takes 2 + 2 + 1)
+template <class T>
+__device__ __forceinline__ cx<T> conj_cross(cx<T> a, cx<T> b, cx<T> c, cx<T> d)
+{
+    T re = c.im * d.im;
+    re = fmaf_t(-c.re, d.re, re);
+    re = fmaf_t(-a.im, b.im, re);
+    re = fmaf_t(a.re, b.re, re);
+    T im = c.im * d.re;
+    im = fmaf_t(c.re, d.im, im);
+    im = fmaf_t(-a.im, b.re, im);
+    im = fmaf_t(-a.re, b.im, im);
+    return {re, im};
+}
+
 template <class T>
 __device__ __forceinline__ void recon_row2(cx<T> W[9])
 {
     // row 2 = conj(row0 x row1)
-    W[6] = cconj(W[1] * W[5] - W[2] * W[4]);
-    W[7] = cconj(W[2] * W[3] - W[0] * W[5]);
-    W[8] = cconj(W[0] * W[4] - W[1] * W[3]);
+    W[6] = conj_cross(W[1], W[5], W[2], W[4]);
+    W[7] = conj_cross(W[2], W[3], W[0], W[5]);
+    W[8] = conj_cross(W[0], W[4], W[1], W[3]);
+}
+
+// sum_b W[r][b] h[b] (row r of a 3x3 complex matrix times a colour vector) as one chain of fused
+// multiply-adds per component: 1 multiply + 5 FMAs, where summing three complex products formed
+// separately takes 8 instructions per component
+template <class T>
+__device__ __forceinline__ cx<T> row_dot(const cx<T> W[9], int r, const cx<T> h[3])
+{
+    const cx<T> a = W[r * 3], b = W[r * 3 + 1], c = W[r * 3 + 2];
+    T re = -c.im * h[2].im;
+    re = fmaf_t(c.re, h[2].re, re);
+    re = fmaf_t(-b.im, h[1].im, re);
+    re = fmaf_t(b.re, h[1].re, re);
+    re = fmaf_t(-a.im, h[0].im, re);
+    re = fmaf_t(a.re, h[0].re, re);
+    T im = c.im * h[2].re;
+    im = fmaf_t(c.re, h[2].im, im);
+    im = fmaf_t(b.im, h[1].re, im);
+    im = fmaf_t(b.re, h[1].im, im);
+    im = fmaf_t(a.im, h[0].re, im);
+    im = fmaf_t(a.re, h[0].im, im);
+    return {re, im};
 }
 
 // 8-real FP16 links: one 16-byte chunk per link holding u01, u02, u10 and the phases of u00 and

@@ -110,8 +110,8 @@ __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int 
     } else {
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            g1[a] = W[a * 3] * h1[0] + W[a * 3 + 1] * h1[1] + W[a * 3 + 2] * h1[2];
-            g2[a] = W[a * 3] * h2[0] + W[a * 3 + 1] * h2[1] + W[a * 3 + 2] * h2[2];
+            g1[a] = row_dot(W, a, h1);
+            g2[a] = row_dot(W, a, h2);
         }
     }
     if constexpr (MU == 3) {
@@ -199,7 +199,7 @@ __device__ __forceinline__ void hop_t_nc(const Geo& g, int x, int y, int z, int 
     for (int a = 0; a < 2; a++)
 #pragma unroll
         for (int c = 0; c < 3; c++)
-            gg[a][c] = unit ? h[a][c] : W[c * 3] * h[a][0] + W[c * 3 + 1] * h[a][1] + W[c * 3 + 2] * h[a][2];
+            gg[a][c] = unit ? h[a][c] : row_dot(W, c, h[a]);
     // twice the product, with the boundary sign and (FP16 input) the site's scale
     const bool flip = g.anti && (D == 0 ? (t == g.T - 1) : (t == 0));
     const T f = (flip ? T(-2) : T(2)) * sc;
