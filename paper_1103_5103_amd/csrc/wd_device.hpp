@@ -145,6 +145,15 @@ __device__ __forceinline__ V gld(const void* base, long idx)
     typedef __attribute__((address_space(1))) const V GV;
     return *((GV*)base + idx);
 }
+// NT: a non-temporal load, for data that the kernel reads once (it does not displace lines that
+// other sites of the launch are about to re-read from L2)
+template <class V, bool NT>
+__device__ __forceinline__ V gldt(const void* base, long idx)
+{
+    typedef __attribute__((address_space(1))) const V GV;
+    if constexpr (NT) return __builtin_nontemporal_load((GV*)base + idx);
+    else return *((GV*)base + idx);
+}
 template <class V, bool NT = false>
 __device__ __forceinline__ void gst(void* base, long idx, V v)
 {
@@ -163,27 +172,27 @@ struct SpinorRef {
 template <int SF> struct SReal { using T = float; };
 template <> struct SReal<SF64> { using T = double; };
 
-template <int SF, class T>
+template <int SF, class T, bool NT = false>
 __device__ __forceinline__ void load_spinor(const SpinorRef& r, long i, cx<T> v[12])
 {
     if constexpr (SF == SF64) {
 #pragma unroll
         for (int j = 0; j < 12; j++) {
-            d2v q = gld<d2v>(r.p, chunk_at(12, r.cs, i, j));
+            d2v q = gldt<d2v, NT>(r.p, chunk_at(12, r.cs, i, j));
             v[j] = mk<T>((T)q[0], (T)q[1]);
         }
     } else if constexpr (SF == SF32) {
 #pragma unroll
         for (int j = 0; j < 6; j++) {
-            f4v q = gld<f4v>(r.p, chunk_at(6, r.cs, i, j));
+            f4v q = gldt<f4v, NT>(r.p, chunk_at(6, r.cs, i, j));
             v[2 * j] = mk<T>((T)q[0], (T)q[1]);
             v[2 * j + 1] = mk<T>((T)q[2], (T)q[3]);
         }
     } else {
-        const float n = gld<float>(r.nrm, i);
+        const float n = gldt<float, NT>(r.nrm, i);
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            h8 q = gld<h8>(r.p, chunk_at(3, r.cs, i, j));
+            h8 q = gldt<h8, NT>(r.p, chunk_at(3, r.cs, i, j));
 #pragma unroll
             for (int k = 0; k < 4; k++) v[4 * j + k] = mk<T>((T)((float)q[2 * k] * n), (T)((float)q[2 * k + 1] * n));
         }

@@ -294,8 +294,10 @@ __device__ __forceinline__ int tiled_block(const HopJob& J, int lb)
 
 // TG: some job of the launch has temporal-gauge links (TG = false compiles the unit-link paths out).
 // NTL: the links are loaded non-temporally, so that they do not evict the neighbour spinors from
-// L2; launches with interleaved systems (links shared through L2) take ordinary loads. A compile-
-// time choice: as a run-time branch the compiler merges the two identical loads and drops the hint.
+// L2; launches with interleaved systems (links shared through L2) take ordinary loads. The same
+// variant loads the epilogue's own-site fields (x0, x1, z), which are read once, non-temporally and
+// stores the output non-temporally. A compile-time choice: as a run-time branch the compiler merges
+// the two identical loads and drops the hint.
 template <int SF, int LF, bool DAG, int RED, int FIN, bool STG, bool NTL, bool TG>
 __global__ __launch_bounds__(BLOCK) void k_hop(
     const HopJob* __restrict__ jobs, int njobs, SysState* __restrict__ sys, int gated, int* exec)
@@ -338,14 +340,14 @@ __global__ __launch_bounds__(BLOCK) void k_hop(
         for (int k = 0; k < 12; k++) acc[k] = c2 * acc[k];
         cx<T> x0[12];
         if (J.x0.p) {
-            load_spinor<SF, T>(J.x0, cb, x0);
+            load_spinor<SF, T, NTL>(J.x0, cb, x0);
             const T c0 = (T)J.c0;
 #pragma unroll
             for (int k = 0; k < 12; k++) acc[k] = acc[k] + c0 * x0[k];
         }
         if (J.x1.p) {
             cx<T> x1[12];
-            load_spinor<SF, T>(J.x1, cb, x1);
+            load_spinor<SF, T, NTL>(J.x1, cb, x1);
             const T c1 = (T)J.c1;
 #pragma unroll
             for (int k = 0; k < 12; k++) acc[k] = acc[k] + c1 * x1[k];
@@ -353,7 +355,7 @@ __global__ __launch_bounds__(BLOCK) void k_hop(
         store_spinor<SF, T, NTL>(J.out, cb, acc);
         if constexpr (RED == RED_ZDOT) {
             cx<T> z[12];
-            load_spinor<SF, T>(J.z, cb, z);
+            load_spinor<SF, T, NTL>(J.z, cb, z);
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 v[0] += (double)z[k].re * acc[k].re + (double)z[k].im * acc[k].im;
