@@ -120,6 +120,23 @@ __host__ __device__ __forceinline__ int nb_index(const Geo& g, int x, int y, int
     if constexpr (MU == 3) t = D == 0 ? (t + 1 == g.T ? 0 : t + 1) : (t == 0 ? g.T - 1 : t - 1);
     return cb_index(g, x, y, z, t);
 }
+// The same neighbour index from the site's own checkerboard index cb = (x >> 1) + Xh (y + Y (z + Z t)):
+// an x step changes x >> 1 by 0 or +-1, a y, z or t step moves by a whole row, plane or slice
+// (a uniform stride), with the periodic wrap. Cheaper than nb_index (no per-lane multiplies).
+template <int MU, int D>
+__host__ __device__ __forceinline__ int nb_from_cb(const Geo& g, int cb, int x, int y, int z, int t)
+{
+    if constexpr (MU == 0) {
+        const int xn = D == 0 ? (x + 1 == g.X ? 0 : x + 1) : (x == 0 ? g.X - 1 : x - 1);
+        return cb - (x >> 1) + (xn >> 1);
+    } else {
+        const int L = MU == 1 ? g.Y : MU == 2 ? g.Z : g.T;
+        const int c = MU == 1 ? y : MU == 2 ? z : t;
+        const int s = MU == 1 ? g.Xh : MU == 2 ? g.Xh * g.Y : g.Xh * g.Y * g.Z;
+        if constexpr (D == 0) return c + 1 == L ? cb - s * (L - 1) : cb + s;
+        else return c == 0 ? cb + s * (L - 1) : cb - s;
+    }
+}
 
 // ---------------------------------------------------------------- chunk addressing
 // Fields and links are stored in blocks of AOSOA_B sites with all chunks of a block contiguous

@@ -71,7 +71,7 @@ template <int MU, int D, bool DAG, int SFI, bool STG, class T>
 __device__ __forceinline__ void hop_dir(const Geo& g, int cb, int x, int y, int z, int t, const HopIn<SFI, STG>& in,
                                         const cx<T> W[9], cx<T> acc[12], int dep, bool unit)
 {
-    const int nb = nb_index<MU, D>(g, x, y, z, t) + dep;
+    const int nb = nb_from_cb<MU, D>(g, cb, x, y, z, t) + dep;
 
     cx<T> psi[12];
     T sc = T(1);  // FP16 input: the site's scale, applied in the accumulation
@@ -186,12 +186,12 @@ __device__ __forceinline__ T load_spin_pair(const SpinorRef& r, long i, cx<T> h[
 // link and adds twice the product to the same two components of the output: no projection sums,
 // half the expansion, half the neighbour bytes of the chiral time hop.
 template <int D, bool DAG, int SFI, class T>
-__device__ __forceinline__ void hop_t_nc(const Geo& g, int x, int y, int z, int t, const SpinorRef& in,
+__device__ __forceinline__ void hop_t_nc(const Geo& g, int cb, int x, int y, int z, int t, const SpinorRef& in,
                                          const cx<T> W[9], cx<T> acc[12], int dep, bool unit)
 {
     constexpr bool minus = (D == 0) != DAG;  // projector 1 - gamma_4
     constexpr int S0 = minus ? 2 : 0;
-    const int nb = nb_index<3, D>(g, x, y, z, t) + dep;
+    const int nb = nb_from_cb<3, D>(g, cb, x, y, z, t) + dep;
     cx<T> h[2][3];
     const T sc = load_spin_pair<SFI, S0, T>(in, nb, h);
     cx<T> gg[2][3];
@@ -249,9 +249,9 @@ __device__ __forceinline__ void hop_axis(const Geo& g, int cb, int x, int y, int
         load_link_pair<LF, T, NTL>(links, lcs, MU, cb + dep, Wf, Wb);
     }
     if (MU == 3 && in.nc) {
-        hop_t_nc<0, DAG, SFI, T>(g, x, y, z, t, in.in, Wf, acc, dep, unit_f);
+        hop_t_nc<0, DAG, SFI, T>(g, cb, x, y, z, t, in.in, Wf, acc, dep, unit_f);
         group_barrier<2 * MU, G>(acc, dep);
-        hop_t_nc<1, DAG, SFI, T>(g, x, y, z, t, in.in, Wb, acc, dep, unit_b);
+        hop_t_nc<1, DAG, SFI, T>(g, cb, x, y, z, t, in.in, Wb, acc, dep, unit_b);
         group_barrier<2 * MU + 1, G>(acc, dep);
         return;
     }

@@ -49,8 +49,8 @@ __device__ __forceinline__ void mrhs_axis(const HopJob* __restrict__ jobs, int j
     for (int k = 0; k < KT; k++)
         if (run[k]) {
             if (nc) {
-                hop_t_nc<0, DAG, SF, T>(g, x, y, z, t, jobs[j0 + k].in, Wf, acc[k], dep, unit_f);
-                hop_t_nc<1, DAG, SF, T>(g, x, y, z, t, jobs[j0 + k].in, Wb, acc[k], dep, unit_b);
+                hop_t_nc<0, DAG, SF, T>(g, cb, x, y, z, t, jobs[j0 + k].in, Wf, acc[k], dep, unit_f);
+                hop_t_nc<1, DAG, SF, T>(g, cb, x, y, z, t, jobs[j0 + k].in, Wb, acc[k], dep, unit_b);
                 continue;
             }
             const HopIn<SF, true> in{jobs[j0 + k].in, stg[k], base, nsl, tg, false};
