@@ -77,6 +77,59 @@ def test_lowprec_operator_full_size(big, fmt):
         del out
 
 
+@pytest.mark.parametrize("fmt,rhs", [("f32/f16", -1), ("f32/f16", 0), ("f16/f16", 2)])
+def test_lowprec_operator_full_size_nonchiral(big, fmt, rhs):
+    """The benchmark's handle (non-chiral spin basis) at 32^3x64: the low-precision operator per
+    site against the oracle's chiral M_prec and hopping term (the basis is internal), for one
+    system in the tuned launch configuration (rhs -1) and for two systems in one launch, as
+    interleaved block pairs (rhs 0) or in the multi-RHS hop (rhs 2, the batched FP16 solves'
+    choice at this size); each copy also against the same system alone. Tolerances as in
+    test_gpu_lowprec (1e-2 with FP16 storage)."""
+    dims, U, b, _ = big
+    spinor, links = fmt.split("/")
+    kappa = 0.134
+    odd = oracle.parity_mask(dims)
+    srcs = [b, li.gaussian_field(dims, 2003)]
+    refs = []
+    for s in srcs:
+        pe = s.copy()
+        pe[odd] = 0
+        ref = oracle.mprec(U, kappa, pe)
+        ref[odd] = oracle.hopping(U, pe)[odd]
+        refs.append(ref)
+    g = wd.wd_gauge_create(_t(U), hint=wd.params(nonchiral=True))
+    try:
+        p = wd.params(spinor=spinor, links=links)
+        for red in ("none", "zdot", "outx"):
+            if rhs < 0:
+                out, dots = wd.wd_apply_prec(g, kappa, _t(b), p=p, v=wd.op_variant(red=red))
+                outs = [_n(out)]
+            else:
+                out, dots = wd.wd_apply_prec(g, kappa, _t(np.stack(srcs)), p=p,
+                                             v=wd.op_variant(red=red, copies=2, rhs_per_thread=rhs))
+                outs = list(_n(out))
+            del out
+            for k, o in enumerate(outs):
+                for name, m in (("even", ~odd), ("odd", odd)):
+                    d = np.linalg.norm((o[m] - refs[k][m]).reshape(-1, 12), axis=1)
+                    scale = np.sqrt(np.mean(np.linalg.norm(refs[k][m].reshape(-1, 12), axis=1) ** 2))
+                    _say("32^3x64 non-chiral operator", fmt, "rhs", rhs, red, "copy", k, name, "max",
+                         d.max() / scale, "rms", np.sqrt(np.mean(d ** 2)) / scale)
+                    assert d.max() / scale < 1e-2
+                if red == "outx":
+                    e = o[~odd].reshape(-1)
+                    assert abs(dots[k, 2] - np.vdot(e, e).real) < 1e-2 * np.vdot(e, e).real
+                if rhs >= 0:
+                    alone, _ = wd.wd_apply_prec(g, kappa, _t(srcs[k]), p=p,
+                                                v=wd.op_variant(red=red, rhs_per_thread=0, tile=0))
+                    alone = _n(alone)
+                    d = np.linalg.norm((o - alone).reshape(-1, 12), axis=1)
+                    assert d.max() / np.sqrt(np.mean(np.linalg.norm(alone.reshape(-1, 12), axis=1) ** 2)) < 1e-2
+                    del alone
+    finally:
+        g.close()
+
+
 def test_mixed_solve_full_size_bench_config(big):
     """The benchmark's sequential mixed solve (FP32 spinors, FP16 links, delta 1e-3, poly guess)
     for the lightest and heaviest masses of the 8."""
