@@ -276,8 +276,8 @@ __device__ __forceinline__ void store_spinor(const SpinorRef& r, long i, const c
 // A hop block covers BLOCK consecutive checkerboard sites, i.e. whole rows of constant (y, z, t)
 // when Xh divides BLOCK. Its x neighbours lie in the same rows and its y neighbours one row up
 // or down, so the block first copies the input sites [cb0 - H, cb0 + BLOCK + H) with H = Xh
-// (when Xh <= STG_H_MAX) into LDS with aligned, coalesced loads, and the four x and y
-// directions then read LDS instead of gathering from memory. Neighbours outside that window
+// (when Xh <= STG_H_MAX) into LDS with coalesced direct global -> LDS loads (stage_window), and
+// the four x and y directions then read LDS instead of gathering from memory. Neighbours outside that window
 // (the periodic wrap in y, or H = 0) are loaded from memory as before.
 constexpr int STG_H_MAX = 32;
 constexpr int STG_SLOTS = BLOCK_SITES + 2 * STG_H_MAX;
@@ -295,21 +295,41 @@ template <> struct Stg<SF16, true> {
     float n[STG_SLOTS];
 };
 
-// copy input site i into slot k
-template <int SF>
-__device__ __forceinline__ void stage_site(Stg<SF, true>& L, int k, const SpinorRef& r, long i)
+// Stage the window [base, base + nsl) with direct global -> LDS loads: each wave covers 64
+// consecutive slots, lane l filling slot k0 + l (the hardware writes lane l's bytes at the wave's
+// LDS address plus l times the access size), so the data does not pass through registers. Sites
+// outside the lattice are skipped (their slots are never read). Ends with the loads complete.
+__device__ __forceinline__ void lds_load16(const void* g, void* lds)
 {
-    if constexpr (SF == SF64) {
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)g,
+                                     (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+__device__ __forceinline__ void lds_load4(const void* g, void* lds)
+{
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)g,
+                                     (__attribute__((address_space(3))) void*)lds, 4, 0, 0);
+}
+template <int SF>
+__device__ __forceinline__ void stage_window(Stg<SF, true>& L, const SpinorRef& r, int base, int nsl, int Vh)
+{
+    const int lane = threadIdx.x & 63;
+    for (int k0 = (int)(threadIdx.x & ~63u); k0 < nsl; k0 += BLOCK_SITES) {
+        const int k = k0 + lane, i = base + k;
+        if (k < nsl && i >= 0 && i < Vh) {
+            if constexpr (SF == SF64) {
 #pragma unroll
-        for (int j = 0; j < 12; j++) L.c[j][k] = gld<d2v>(r.p, chunk_at(12, r.cs, i, j));
-    } else if constexpr (SF == SF32) {
+                for (int j = 0; j < 12; j++) lds_load16((const d2v*)r.p + chunk_at(12, r.cs, i, j), &L.c[j][k0]);
+            } else if constexpr (SF == SF32) {
 #pragma unroll
-        for (int j = 0; j < 6; j++) L.c[j][k] = gld<f4v>(r.p, chunk_at(6, r.cs, i, j));
-    } else {
-        L.n[k] = gld<float>(r.nrm, i);
+                for (int j = 0; j < 6; j++) lds_load16((const f4v*)r.p + chunk_at(6, r.cs, i, j), &L.c[j][k0]);
+            } else {
+                lds_load4(r.nrm + i, &L.n[k0]);
 #pragma unroll
-        for (int j = 0; j < 3; j++) L.c[j][k] = gld<h8>(r.p, chunk_at(3, r.cs, i, j));
+                for (int j = 0; j < 3; j++) lds_load16((const h8*)r.p + chunk_at(3, r.cs, i, j), &L.c[j][k0]);
+            }
+        }
     }
+    __builtin_amdgcn_s_waitcnt(0);
 }
 
 template <int SF, class T>

@@ -326,10 +326,7 @@ __global__ __launch_bounds__(BLOCK) void k_hop(
         const int H = J.g.Xh <= STG_H_MAX ? J.g.Xh : 0;
         base = cb0 - H;
         nsl = BLOCK + 2 * H;
-        for (int k = threadIdx.x; k < nsl; k += BLOCK) {
-            const int i = base + k;
-            if (i >= 0 && i < J.g.Vh) stage_site<SF>(stg, k, J.in, i);
-        }
+        stage_window<SF>(stg, J.in, base, nsl, J.g.Vh);
         __syncthreads();
     }
     const HopIn<SF, STG> hin{J.in, stg, base, nsl, TG && J.tg != 0, J.nc != 0};

@@ -90,11 +90,7 @@ __global__ __launch_bounds__(BLOCK) void k_hop_mrhs(const HopJob* __restrict__ j
     const int base = cb0 - H, nsl = BLOCK + 2 * H;
 #pragma unroll
     for (int k = 0; k < KT; k++)
-        if (run[k])
-            for (int i = threadIdx.x; i < nsl; i += BLOCK) {
-                const int site = base + i;
-                if (site >= 0 && site < J0.g.Vh) stage_site<SF>(stg[k], i, jobs[j0 + k].in, site);
-            }
+        if (run[k]) stage_window<SF>(stg[k], jobs[j0 + k].in, base, nsl, J0.g.Vh);
     __syncthreads();
     double v[KT][NRED];
 #pragma unroll
