@@ -241,8 +241,12 @@ HopChoice tune_hop(wd_gauge* g, int sf, int lf, hipStream_t st, int nshared)
     char key[160];
     std::snprintf(key, sizeof(key), "%s|%dx%dx%dx%d|sf%d|lf%d|tg%d|n%d", arch_name().c_str(), G.X, G.Y, G.Z, G.T, sf, lf,
                   (int)g->tg, nc);
+    // a cached choice counts only if it is one of this configuration's candidates (the file may be
+    // stale or edited by hand)
     auto it = tune_cache().find(key);
-    if (it != tune_cache().end()) return it->second;
+    if (it != tune_cache().end())
+        for (const HopChoice& c : cands)
+            if (c.tz == it->second.tz && c.rhs == it->second.rhs) return c;
     g->ensure_slinks(lf, st);
     std::vector<Field> in(nc), out(nc);
     for (int k = 0; k < nc; k++) {
