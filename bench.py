@@ -20,9 +20,11 @@ pass runs each method on its own with the events on. The batched solve's hop rea
 for all systems of a launch (they share the gauge field), so its compulsory bytes count the links
 once; it is reported separately. Beside the step, bench.py also times the paper's defect-correction
 scheme, the start-guess gain against its order, the three methods on a handle that solves in
-temporal gauge, the normal equations (CG-M against single-shift CG), and the sequential and
-batched solves with other storage (8-real FP16 links; FP16 spinors). The CPU baseline is the
-plain FP64 oracle on the host cores.
+temporal gauge, the normal equations (CG-M against single-shift CG), the sequential and
+batched solves with other storage (8-real FP16 links; FP16 spinors), and the paper's Table 3
+experiment: its wide and narrow mass sets (Table 2's spacings) placed near the critical point of
+these links, single-mass against multi-shift. The CPU baseline is the plain FP64 oracle on the host
+cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 32x64|16x32] [--no-cpu]
 """
@@ -179,6 +181,61 @@ def normal_equations(torch, wd, np, g, bd, kappa, W, reps):
                      "reliable_updates": [s["reliable_updates"] for s in st],
                      "max_true_rel_res": float(f"{max(s['true_rel_res'] for s in st):.3e}")}
     out["speedup_sequential_vs_cg_m"] = round(out["cg_m_fp64"]["solve_s"] / out["cg_sequential_mixed"]["solve_s"], 3)
+    return out
+
+
+# Table 2's two mass sets, a m in lattice units (the paper's quenched ensemble: a m_c = -0.8173)
+PAPER_WIDE_AM = [-0.7908, -0.7721, -0.7511, -0.7320, -0.7105, -0.6193, -0.5108, -0.2687]
+PAPER_NARROW_AM = [-0.7908, -0.7887, -0.7866, -0.7846, -0.7825, -0.7804, -0.7784, -0.7763]
+# lightest mass of the sets on the benchmark's near-Haar links: FP64 even-odd BiCGstab needs about
+# 140 iterations there, as the paper's lightest masses needed 120-175 (its critical point is not
+# the paper's: near-Haar links put it near kappa = 0.25)
+NEAR_CRITICAL_KAPPA = 0.237
+
+
+def mass_sets_near_critical(torch, wd, np, g, bd, U, b, W, reps, check):
+    """Table 3 of the paper on this lattice: its wide and narrow 8-mass sets (Table 2's spacings in
+    a m, shifted so that the lightest mass sits at NEAR_CRITICAL_KAPPA), solved by the sequential
+    mixed single-mass solver with and without the start guess and by FP64 BiCGstab-M; total
+    iterations, time per iteration, solve time, speed-up, and (check) the oracle residual of every
+    mass of every method."""
+    am1 = 1 / (2 * NEAR_CRITICAL_KAPPA) - 4
+    pm = wd.params(tol=1e-8, spinor=W["spinor"], links=W["links"], delta=W["delta"], max_iter=4000)
+    pf = wd.params(tol=1e-8, mixed=False, eo=False, max_iter=4000)
+    _, st0 = wd.bicgstab_solve(g, NEAR_CRITICAL_KAPPA, bd, p=wd.params(tol=1e-8, mixed=False, max_iter=4000))
+    out = {"lightest_kappa": NEAR_CRITICAL_KAPPA, "fp64_even_odd_iters_at_lightest": st0["iters"]}
+    for name, ams in (("wide", PAPER_WIDE_AM), ("narrow", PAPER_NARROW_AM)):
+        kappas = [1 / (2 * (am1 + a - ams[0] + 4)) for a in ams]
+        runs = {"single_mass": lambda: wd.wd_multimass_solve(g, kappas, bd, p=pm),
+                "single_mass_no_guess": lambda: wd.wd_multimass_solve(g, kappas, bd, guess=wd.WD_GUESS_NONE, p=pm),
+                "multishift": lambda: wd.bicgstab_m_solve(g, kappas, bd, p=pf)}
+        t = {k: [] for k in runs}
+        res = {}
+        for rep in range(reps + 1):
+            for k, fn in runs.items():
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                xs, sts = fn()
+                torch.cuda.synchronize()
+                if rep > 0:
+                    t[k].append(time.perf_counter() - a)
+                res[k] = (xs, sts)
+        o = {"kappas": [round(k, 5) for k in kappas]}
+        for k, (xs, sts) in res.items():
+            its = [s["iters"] for s in sts]
+            ts = float(np.median(t[k]))
+            # the multi-shift solver runs one Krylov space: its iterations are those of the base
+            total = max(its) if k == "multishift" else sum(its)
+            o[k] = {"solve_s": round(ts, 4), "iters": its, "total_iters": total,
+                    "ms_per_iter": round(ts / total * 1e3, 3),
+                    "reliable_updates": [s["reliable_updates"] for s in sts]}
+            if check:
+                import oracle
+                o[k]["oracle_true_rel_res"] = [float(f"{oracle.true_residual(U, kk, x.cpu().numpy(), b):.3e}")
+                                              for kk, x in zip(kappas, xs)]
+        o["speedup_single_mass_vs_multishift"] = round(o["multishift"]["solve_s"] / o["single_mass"]["solve_s"], 3)
+        o["speedup_no_guess_vs_multishift"] = round(o["multishift"]["solve_s"] / o["single_mass_no_guess"]["solve_s"], 3)
+        out[name] = o
     return out
 
 
@@ -555,9 +612,13 @@ def main():
             log(f"oracle residuals: max {oracle_res['max']:.2e}")
         except Exception as e:
             oracle_res = {"error": repr(e)}
-    normal = link8 = spin16 = None
+    normal = link8 = spin16 = sets = None
     if not args.no_extras:
         normal = normal_equations(torch, wd, np, g, bd, kappas[-1], W, args.steps)
+        if args.workload == "32x64":
+            sets = mass_sets_near_critical(torch, wd, np, g, bd, U, b, W, min(args.steps, 2), not args.no_cpu)
+            log("mass sets near criticality: wide", sets["wide"]["speedup_single_mass_vs_multishift"], "narrow",
+                sets["narrow"]["speedup_single_mass_vs_multishift"])
         if W["links"] == "f16":
             link8 = storage_variant(torch, wd, np, g, bd, kappas, W, args.steps, instrumented, gbs, W["spinor"], 8)
         if W["spinor"] == "f32":
@@ -706,6 +767,7 @@ def main():
         "chiral_basis": chiral,
         "temporal_gauge": temporal,
         "normal_equations_cg": normal,
+        "mass_sets_near_critical": sets,
         "links_8real": link8,
         "spinors_f16": spin16,
         "batched_96_systems": extra["batched"],
