@@ -197,8 +197,8 @@ def mass_sets_near_critical(torch, wd, np, g, bd, U, b, W, reps, check):
     """Table 3 of the paper on this lattice: its wide and narrow 8-mass sets (Table 2's spacings in
     a m, shifted so that the lightest mass sits at NEAR_CRITICAL_KAPPA), solved by the sequential
     mixed single-mass solver with and without the start guess and by FP64 BiCGstab-M; total
-    iterations, time per iteration, solve time, speed-up, and (check) the oracle residual of every
-    mass of every method."""
+    iterations, time per iteration, solve time, speed-up, the start guesses' gain against their
+    order (Fig. 6), and (check) the oracle residual of every mass of every method."""
     am1 = 1 / (2 * NEAR_CRITICAL_KAPPA) - 4
     pm = wd.params(tol=1e-8, spinor=W["spinor"], links=W["links"], delta=W["delta"], max_iter=4000)
     pf = wd.params(tol=1e-8, mixed=False, eo=False, max_iter=4000)
@@ -233,6 +233,17 @@ def mass_sets_near_critical(torch, wd, np, g, bd, U, b, W, reps, check):
                 import oracle
                 o[k]["oracle_true_rel_res"] = [float(f"{oracle.true_residual(U, kk, x.cpu().numpy(), b):.3e}")
                                               for kk, x in zip(kappas, xs)]
+        # Fig. 6 for this set: total iterations with the guess from the k most recent solutions over
+        # those with zero start vectors, for both guesses
+        def total(guess, order):
+            q = wd.params(tol=1e-8, spinor=W["spinor"], links=W["links"], delta=W["delta"], max_iter=4000,
+                          guess_order=order)
+            return sum(st["iters"] for st in wd.wd_multimass_solve(g, kappas, bd, guess=guess, p=q)[1])
+        base = o["single_mass_no_guess"]["total_iters"]
+        o["guess_gain_vs_order"] = {
+            "baseline_iters": base,
+            "poly": [round(total(wd.WD_GUESS_POLY, k) / base, 3) for k in range(1, len(kappas))],
+            "minres": [round(total(wd.WD_GUESS_MINRES, k) / base, 3) for k in range(1, len(kappas))]}
         o["speedup_single_mass_vs_multishift"] = round(o["multishift"]["solve_s"] / o["single_mass"]["solve_s"], 3)
         o["speedup_no_guess_vs_multishift"] = round(o["multishift"]["solve_s"] / o["single_mass_no_guess"]["solve_s"], 3)
         out[name] = o
