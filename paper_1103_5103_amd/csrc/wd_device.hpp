@@ -298,7 +298,8 @@ template <> struct Stg<SF16, true> {
 // Stage the window [base, base + nsl) with direct global -> LDS loads: each wave covers 64
 // consecutive slots, lane l filling slot k0 + l (the hardware writes lane l's bytes at the wave's
 // LDS address plus l times the access size), so the data does not pass through registers. Sites
-// outside the lattice are skipped (their slots are never read). Ends with the loads complete.
+// outside the lattice are skipped (their slots are never read). The loads are asynchronous:
+// stage_wait() before the block's barrier completes them (one wait after several windows).
 __device__ __forceinline__ void lds_load16(const void* g, void* lds)
 {
     __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)g,
@@ -329,8 +330,8 @@ __device__ __forceinline__ void stage_window(Stg<SF, true>& L, const SpinorRef& 
             }
         }
     }
-    __builtin_amdgcn_s_waitcnt(0);
 }
+__device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0); }
 
 template <int SF, class T>
 __device__ __forceinline__ void load_spinor_stg(const Stg<SF, true>& L, int k, cx<T> v[12])

@@ -327,6 +327,7 @@ __global__ __launch_bounds__(BLOCK) void k_hop(
         base = cb0 - H;
         nsl = BLOCK + 2 * H;
         stage_window<SF>(stg, J.in, base, nsl, J.g.Vh);
+        stage_wait();
         __syncthreads();
     }
     const HopIn<SF, STG> hin{J.in, stg, base, nsl, TG && J.tg != 0, J.nc != 0};

@@ -91,6 +91,7 @@ __global__ __launch_bounds__(BLOCK) void k_hop_mrhs(const HopJob* __restrict__ j
 #pragma unroll
     for (int k = 0; k < KT; k++)
         if (run[k]) stage_window<SF>(stg[k], jobs[j0 + k].in, base, nsl, J0.g.Vh);
+    stage_wait();
     __syncthreads();
     double v[KT][NRED];
 #pragma unroll
