@@ -250,8 +250,9 @@ typedef struct {
                          WD_RED_NONE; WD_RED_ZDOT <in_e, out_e>; WD_RED_OUTX <out_e, in_e> and
                          |out_e|^2; WD_RED_NORM |out_e|^2 (all sums in FP64)                      */
     int stage;        /* LDS staging of the x and y neighbours: -1 library default, 0 off, 1 on   */
-    int nontemporal;  /* link loads and hop stores: -1 the solvers' policy, 0 ordinary, 1
-                         non-temporal                                                            */
+    int nontemporal;  /* cache policy of the hops: -1 the solvers' policy, 0 ordinary, 1
+                         non-temporal link loads, epilogue-field loads and output stores (the
+                         first, plain hop of a low-precision operator keeps ordinary stores)     */
     int tile;         /* block order: -1 autotuned, 0 site order, tz > 0 t fastest within groups
                          of tz z-planes (site order where the lattice does not allow tz)          */
     int copies;       /* 1..64 systems in one launch; in and out then hold that many fields, one
