@@ -78,3 +78,12 @@ def test_fp16_site_scale(probe):
         else:
             # zero, subnormal, infinite or NaN maxima: no finite site value may become 0 * inf
             assert inv == 0.0, (m, inv)
+
+
+def test_random_shapes(probe):
+    """The same map checks on seeded random even shapes (rows from 1 to 40 checkerboard sites)."""
+    rng = np.random.default_rng(7)
+    for _ in range(6):
+        dims = tuple(int(2 * rng.integers(1, 5)) for _ in range(3)) + (int(2 * rng.integers(1, 4)),)
+        dims = (int(2 * rng.integers(1, 41)),) + dims[1:]
+        test_checkerboard_map_and_neighbours(probe, dims)
