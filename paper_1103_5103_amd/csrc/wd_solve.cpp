@@ -339,8 +339,10 @@ static HopJob hop_job(const Geo& g, int parity, int sys, const SpinorRef& in, co
 
 // Hop jobs that share their links (same gauge field and parity) run in interleaved block groups of
 // at most kIlvMax systems: pairs share the link loads while the neighbour spinors of both still fit
-// the L2 reuse window (measured at 32^3x64 with 8 systems: 660 / 673 / 712 / 693 us per hop for
-// groups of 2 / 3 / 4 / 8).
+// the L2 reuse window. Measured at 32^3x64 with 8 systems (FP16 links, FP32 spinors): pairs at
+// their best block order (tz = 16) 585 us per hop and 57.3 ms per 8-mass solve, groups of 4 at
+// theirs (tz = 8) 573 us and 56.6 ms, groups of 3 (3 + 3 + 2) at tz = 8 622 us and 59.3 ms. The
+// 1% that groups of 4 gain needs a block order of their own, so pairs stay.
 constexpr int kIlvMax = 2;
 static bool interleave_on() { return true; }
 static int interleave_max() { return kIlvMax; }
