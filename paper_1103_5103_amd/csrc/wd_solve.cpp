@@ -278,9 +278,9 @@ HopChoice tune_hop(wd_gauge* g, int sf, int lf, hipStream_t st, int nshared)
                                     t.host[0].tg, ntl));
         }
     };
-    hipEvent_t e0, e1;
-    WD_CHECK_HIP(hipEventCreate(&e0));
-    WD_CHECK_HIP(hipEventCreate(&e1));
+    hipEvent_t e0, e1;  // timing only: no system-scope fence (L2 writeback and invalidate)
+    WD_CHECK_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    WD_CHECK_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
     // three interleaved passes over the candidates, each candidate's best pass counts (a single
     // pass let the clock and cache state of the moment decide within a few %)
     std::vector<float> cand_ms(cands.size(), 1e30f);
