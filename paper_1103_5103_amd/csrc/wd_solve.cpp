@@ -415,6 +415,24 @@ static double hop_bytes(const JobTable<HopJob>& t, int sf, int lf, int extra_fie
     }
     return n * (2 + extra_fields) * spinor_site_bytes(sf) + nl * link_site_bytes(lf);
 }
+// Compulsory bytes of an OP_INIT launch, per job from its flags: r_hi read (FP64), r_lo written,
+// rhat written (flags 1) or read (when it is a field of its own: CG passes r_lo), s written
+// (flags 2), p read and written (flags 8), x_lo cleared (flags 4; FP32 storage for the 16-bit
+// formats)
+static double init_bytes(const JobTable<SweepJob>& t, int sfl)
+{
+    const double bl = spinor_site_bytes(sfl), bx = spinor_site_bytes(sfl == SF64 ? SF64 : SF32);
+    double n = 0;
+    for (auto& j : t.host) {
+        double b = spinor_site_bytes(SF64) + bl;
+        if ((j.flags & 1) || j.f[R_F2].p != j.f[R_F0].p) b += bl;
+        if (j.flags & 2) b += bl;
+        if (j.flags & 8) b += 2 * bl;
+        if (j.flags & 4) b += bx;
+        n += (double)j.n * b;
+    }
+    return n;
+}
 static double sweep_bytes(const JobTable<SweepJob>& t, double per_site)
 {
     double n = 0;
@@ -727,7 +745,7 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         for (auto& j : InitFirst.host) j.f[R_F1] = S[j.sys].BP.all();
         InitFirst.upload(st);
     }
-    run_sweep(OP_INIT, SFL, InitFirst, sys.d(), GATE_RUN, st, 0);
+    run_sweep(OP_INIT, SFL, InitFirst, sys.d(), GATE_RUN, st, init_bytes(InitFirst, SFL));
     for (int i = 0; i < n; i++) S[i].t0 = t_start;
 
     const double bl = spinor_site_bytes(SFL), bx = spinor_site_bytes(SFX);
@@ -840,8 +858,8 @@ static void eo_solve(std::vector<EoSys>& S, const wd_solver_params& P, hipStream
         }
         sys.upload(st);
         // the restart finishers set the continuing systems RUNNING again
-        if (any_next) run_sweep(OP_INIT, SFL, InitRel, sys.d(), 1 << ST_SEL1, st, 0);
-        if (any_fresh) run_sweep(OP_INIT, SFL, InitRestart, sys.d(), 1 << ST_SEL2, st, 0);
+        if (any_next) run_sweep(OP_INIT, SFL, InitRel, sys.d(), 1 << ST_SEL1, st, init_bytes(InitRel, SFL));
+        if (any_fresh) run_sweep(OP_INIT, SFL, InitRestart, sys.d(), 1 << ST_SEL2, st, init_bytes(InitRestart, SFL));
     }
 
     // ---- finish: odd half from eq. eo3, unpack. With x_o from eq. eo3 the full residual is
@@ -1003,7 +1021,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
     for (auto* t : {&Init, &SW, &SXR, &SEND}) layout(*t);
     for (auto* t : {&HAs, &HAw}) layout(*t);
     upload_tables(st, g->raw["ms.tables"], {&Init, &SW, &SXR, &SEND, &HAs, &HAw});
-    run_sweep(OP_MSINIT, SF64, Init, sys.d(), 0, st, 0);
+    run_sweep(OP_MSINIT, SF64, Init, sys.d(), 0, st, sweep_bytes(Init, (4 + 2 * ns) * 192.0));
     sys.download(st);
     const double bb = sys.h[0].red[2];
     sys.h[0].target2 = P.tol * P.tol * bb;
@@ -1014,11 +1032,11 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
     sys.upload(st);
 
     const int endop = ns > 0 ? OP_SHIFT : OP_S;
-    const double bH = hop_bytes(HAs, SF64, L64, 2);
+    const double bH = hop_bytes(HAs, SF64, L64, 2), bHw = hop_bytes(HAw, SF64, L64, 1);
     auto iterate = [&](int active_shifts, hipStream_t q) {
         run_hop(SF64, L64, false, RED_ZDOT, FIN_BETA, HAs, sys.d(), GATE_RUN, q, bH);
         run_sweep(OP_W, SF64, SW, sys.d(), GATE_RUN, q, sweep_bytes(SW, 3 * 192));
-        run_hop(SF64, L64, false, RED_OUTX, FIN_CHI, HAw, sys.d(), GATE_RUN, q, bH - nsites * 192.0 / 2);
+        run_hop(SF64, L64, false, RED_OUTX, FIN_CHI, HAw, sys.d(), GATE_RUN, q, bHw);
         run_sweep(OP_XR, SF64, SXR, sys.d(), GATE_RUN, q, sweep_bytes(SXR, 7 * 192));
         run_sweep(endop, SF64, SEND, sys.d(), GATE_RUN, q, sweep_bytes(SEND, (ns > 0 ? 6 : 4) * 192 + 4 * 192 * active_shifts));
     };
@@ -1096,7 +1114,7 @@ static wd_status ms_solve(wd_gauge* g, int nk, const double* kappas, double* con
         layout(R);
         upload_tables(st, g->raw["ms.rtables"], {&R});
         rs.upload(st);
-        run_hop(SF64, L64, false, RED_NORM, FIN_STORE, R, rs.d(), 0, st, 0);
+        run_hop(SF64, L64, false, RED_NORM, FIN_STORE, R, rs.d(), 0, st, hop_bytes(R, SF64, L64, 2));
         for (int i = 0; i < nk; i++) {
             const Field& Xi = i == base ? X : XS[shift_of[i]];
             WD_CHECK_HIP(launch_unpack_spinor(SF64, x[i], geo, Xi.half(0), Xi.half(1), P.dagger, 1.0, st, g->gm(), g->nc));
@@ -1806,7 +1824,7 @@ static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream
         for (auto& j : InitFirst.host) j.f[R_F1] = S[j.sys].src.B64.half(0);
         InitFirst.upload(st);
     }
-    run_sweep(OP_INIT, SFL, InitFirst, sys.d(), GATE_RUN, st, 0);
+    run_sweep(OP_INIT, SFL, InitFirst, sys.d(), GATE_RUN, st, init_bytes(InitFirst, SFL));
     for (int i = 0; i < n; i++) S[i].t0 = t_start;
 
     const double bH = hop_bytes(H1, SFL, LFL, 0), bH2 = hop_bytes(H2, SFL, LFL, 1), bH4 = hop_bytes(H4, SFL, LFL, 2);
@@ -1913,8 +1931,8 @@ static void cg_solve(std::vector<CgSys>& S, const wd_solver_params& P, hipStream
             }
         }
         sys.upload(st);
-        if (any_next) run_sweep(OP_INIT, SFL, InitRel, sys.d(), 1 << ST_SEL1, st, 0);
-        if (any_fresh) run_sweep(OP_INIT, SFL, InitRestart, sys.d(), 1 << ST_SEL2, st, 0);
+        if (any_next) run_sweep(OP_INIT, SFL, InitRel, sys.d(), 1 << ST_SEL1, st, init_bytes(InitRel, SFL));
+        if (any_fresh) run_sweep(OP_INIT, SFL, InitRestart, sys.d(), 1 << ST_SEL2, st, init_bytes(InitRestart, SFL));
     }
 
     for (auto& e : S)
@@ -2046,7 +2064,7 @@ static wd_status cgm_solve(wd_gauge* g, double kappa, int n, const double* sigma
     }
     for (auto* t : {&Init, &SX, &SP}) layout(*t);
     upload_tables(st, g->raw["cgm.tables"], {&Init, &SX, &SP, &H1, &H2, &H3, &H4});
-    run_sweep(OP_MSINIT, SF64, Init, sys.d(), 0, st, 0);
+    run_sweep(OP_MSINIT, SF64, Init, sys.d(), 0, st, sweep_bytes(Init, (4 + 2 * ns) * 192.0));
     sys.download(st);
     const double bb = sys.h[0].red[2];
     sys.h[0].target2 = P.tol * P.tol * bb;
@@ -2162,11 +2180,11 @@ static wd_status cgm_solve(wd_gauge* g, double kappa, int n, const double* sigma
         layout(Bs);
         upload_tables(st, g->raw["cgm.rtables"], {&Bs, &Q1, &Q2, &Q3, &Q4});
         rs.upload(st);
-        run_sweep(OP_AXPY, SF64, Bs, rs.d(), 0, st, 0);
-        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Q1, rs.d(), 0, st, 0);
-        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Q2, rs.d(), 0, st, 0);
-        run_hop(SF64, L64, true, RED_NONE, FIN_STORE, Q3, rs.d(), 0, st, 0);
-        run_hop(SF64, L64, true, RED_NORM, FIN_STORE, Q4, rs.d(), 0, st, 0);
+        run_sweep(OP_AXPY, SF64, Bs, rs.d(), 0, st, sweep_bytes(Bs, 3 * 192.0));
+        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Q1, rs.d(), 0, st, hop_bytes(Q1, SF64, L64, 0));
+        run_hop(SF64, L64, false, RED_NONE, FIN_STORE, Q2, rs.d(), 0, st, hop_bytes(Q2, SF64, L64, 1));
+        run_hop(SF64, L64, true, RED_NONE, FIN_STORE, Q3, rs.d(), 0, st, hop_bytes(Q3, SF64, L64, 0));
+        run_hop(SF64, L64, true, RED_NORM, FIN_STORE, Q4, rs.d(), 0, st, hop_bytes(Q4, SF64, L64, 2));
         for (int i = 0; i < n; i++)
             WD_CHECK_HIP(launch_unpack_spinor(SF64, x[i], geo, X[i].half(0), X[i].half(1), 0, 1.0, st, g->gm(), g->nc));
         rs.download(st);
