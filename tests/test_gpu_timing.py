@@ -72,3 +72,35 @@ def test_timing_classes_of_a_solve():
     finally:
         wd.timing_enable(False)
         g.close()
+
+
+def test_multishift_fp64_hop_bytes():
+    """BiCGstab-M (FP64, full lattice, 12-real FP64 links for SU(3) input): per iteration one hop
+    with <rhat, As> (reads the input, s and rhat: 4 spinors + 8 links per site) and one with
+    <Aw, w>, |Aw|^2 (3 spinors + 8 links); at the end one launch forms every mass's true residual
+    (reads x, b and the input: 4 spinors + 8 links per site and mass). Gated launches after
+    convergence are not counted."""
+    U = torch.from_numpy(li.random_links(DIMS, 1.0, 1012)).cuda()
+    b = torch.from_numpy(li.gaussian_field(DIMS, 2012)).cuda()
+    g = wd.wd_gauge_create(U)
+    p = wd.params(tol=1e-8, mixed=False, eo=False)
+    kappas = [0.120, 0.124]
+    try:
+        wd.bicgstab_m_solve(g, kappas, b, p=p)
+        torch.cuda.synchronize()
+        wd.timing_reset()
+        wd.timing_enable(True)
+        _, sts = wd.bicgstab_m_solve(g, kappas, b, p=p)
+        torch.cuda.synchronize()
+        ms, n, by = wd.timing_get(1)
+        wd.timing_enable(False)
+        iters = max(s["iters"] for s in sts)
+        print("fp64 hop class", ms, n, by, "iterations", iters, flush=True)
+        V = 2 * VH
+        spinor64, links64 = 192, 8 * 96
+        assert n == 2 * iters + 1
+        assert by == iters * V * ((4 * spinor64 + links64) + (3 * spinor64 + links64)) + len(kappas) * V * (
+            4 * spinor64 + links64)
+    finally:
+        wd.timing_enable(False)
+        g.close()
