@@ -132,8 +132,6 @@ def check_dots(dots, out, pe, odd, red, tol):
 def test_operator_formats(dims, fmt):
     """Every storage format on every lattice shape, with the solvers' default hop variants; the
     reduction kind rotates with the shape so that each format meets each epilogue."""
-    if fmt.endswith("r8") and dims == (2, 2, 2, 2):
-        pytest.skip("covered on the larger lattices")
     red = ["none", "zdot", "outx", "norm"][SHAPES.index(dims) % 4]
     U = li.random_links(dims, 1.0, 1200 + SHAPES.index(dims))
     psi = li.gaussian_field(dims, 2200 + SHAPES.index(dims))
