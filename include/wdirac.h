@@ -296,9 +296,11 @@ const char* wd_status_str(wd_status s);
 wd_status wd_last_error(char* buf, size_t n);
 
 /*
- * Kernel timing (measurement support, not part of the method). When enabled, the library
- * brackets each launch of the named kernel classes with HIP events on the launch stream and
- * accumulates their durations; reading the totals synchronises the recorded events.
+ * Kernel timing (measurement support, not part of the method). When enabled, each launch of the
+ * named kernel classes is made with a pair of HIP events on the launch stream that take the
+ * kernel's own start and end times (hipExtLaunchKernel), and their durations are accumulated;
+ * reading the totals synchronises the device. Solver iterations are not replayed from graphs
+ * while timing is on.
  * class: 0 = low-precision even-odd hop, 1 = FP64 hop, 2 = fused vector sweeps,
  *        3 = the small finisher kernels that complete the reductions, 4 + r = the low-precision
  *        hops with fused reduction r (WD_RED_NONE .. WD_RED_NORM; also counted in class 0).

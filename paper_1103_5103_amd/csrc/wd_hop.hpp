@@ -381,10 +381,10 @@ __global__ __launch_bounds__(BLOCK) void k_hop(
 static inline dim3 grid1(long nblk) { return dim3((unsigned)nblk); }
 
 #define HOP_LAUNCH(SF_, LF_, DAG_, RED_, FIN_, STG_, TG_)                                                          \
-    if (ntl) hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, STG_, true, TG_>), grid1(nblocks), dim3(BLOCK), 0, s, \
-                                jobs, njobs, sys, gated, exec);                                                    \
-    else hipLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, STG_, false, TG_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs, \
-                       sys, gated, exec)
+    if (ntl) hipExtLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, STG_, true, TG_>), grid1(nblocks), dim3(BLOCK), 0, s, \
+                                   ev0, ev1, 0, jobs, njobs, sys, gated, exec);                                    \
+    else hipExtLaunchKernelGGL((k_hop<SF_, LF_, DAG_, RED_, FIN_, STG_, false, TG_>), grid1(nblocks), dim3(BLOCK), 0, s, \
+                               ev0, ev1, 0, jobs, njobs, sys, gated, exec)
 // The kernel does not depend on the finisher run after it (FIN_ names the instantiation only): the
 // launch is chosen by the reduction kind.
 #define HOP_CASE(SF_, LF_, DAG_, RED_, FIN_)                                                                        \

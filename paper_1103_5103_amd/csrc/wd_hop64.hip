@@ -5,7 +5,8 @@
 namespace wd {
 
 hipError_t launch_hop64(bool dag, int lf, int red, const HopJob* jobs, int njobs, long nblocks, SysState* sys,
-                        int gated, hipStream_t s, int* exec, int stage, int tg, int ntl)
+                        int gated, hipStream_t s, int* exec, int stage, int tg, int ntl, hipEvent_t ev0,
+                        hipEvent_t ev1)
 {
     const int sf = SF64;
     if (stage < 0) stage = hop_stage64_default();

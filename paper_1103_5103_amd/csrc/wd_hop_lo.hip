@@ -5,14 +5,16 @@
 namespace wd {
 
 hipError_t launch_hop64(bool dag, int lf, int red, const HopJob* jobs, int njobs, long nblocks, SysState* sys,
-                        int gated, hipStream_t s, int* exec, int stage, int tg, int ntl);
+                        int gated, hipStream_t s, int* exec, int stage, int tg, int ntl, hipEvent_t ev0,
+                        hipEvent_t ev1);
 
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
-                      SysState* sys, int gated, hipStream_t s, int* exec, int stage, int tg, int ntl)
+                      SysState* sys, int gated, hipStream_t s, int* exec, int stage, int tg, int ntl, hipEvent_t ev0,
+                      hipEvent_t ev1)
 {
     if (tg && dag) return hipErrorInvalidValue;  // the adjoint hop runs on the caller's links only
     if (nblocks <= 0) return hipSuccess;
-    if (sf == SF64) return launch_hop64(dag, lf, red, jobs, njobs, nblocks, sys, gated, s, exec, stage, tg, ntl);
+    if (sf == SF64) return launch_hop64(dag, lf, red, jobs, njobs, nblocks, sys, gated, s, exec, stage, tg, ntl, ev0, ev1);
     if (stage < 0) stage = hop_stage_default();
     const int stage64 = stage;
     HOP_REDS(SF32, L32_12, false)

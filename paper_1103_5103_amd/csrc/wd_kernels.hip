@@ -1058,11 +1058,12 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const double2* __restrict__ xs, 
 
 #define FIN_CASE(NR_, FIN_)                                                                                        \
     if (nr == NR_ && fin == FIN_) {                                                                                \
-        hipLaunchKernelGGL((k_finish<NR_, FIN_>), dim3(nfin), dim3(BLOCK), 0, s, fins, sys, gated);               \
+        hipExtLaunchKernelGGL((k_finish<NR_, FIN_>), dim3(nfin), dim3(BLOCK), 0, s, ev0, ev1, 0, fins, sys, gated); \
         return hipGetLastError();                                                                                  \
     }
 
-hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState* sys, int gated, hipStream_t s)
+hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState* sys, int gated, hipStream_t s,
+                         hipEvent_t ev0, hipEvent_t ev1)
 {
     if (nfin <= 0) return hipSuccess;
     FIN_CASE(3, FIN_STORE)
@@ -1079,7 +1080,8 @@ hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState
 
 #define SWEEP_CASE(OP_, SF_)                                                                                       \
     if (op == OP_ && sfl == SF_) {                                                                                 \
-        hipLaunchKernelGGL((k_sweep<OP_, SF_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs, sys, gated, exec); \
+        hipExtLaunchKernelGGL((k_sweep<OP_, SF_>), grid1(nblocks), dim3(BLOCK), 0, s, ev0, ev1, 0, jobs, njobs, sys, \
+                              gated, exec);                                                                        \
         return hipGetLastError();                                                                                  \
     }
 #define SWEEP_ALL(SF_)                                                                                             \
@@ -1088,7 +1090,7 @@ hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState
     SWEEP_CASE(OP_CGX, SF_) SWEEP_CASE(OP_CGP, SF_)
 
 hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long nblocks, SysState* sys, int gated,
-                        hipStream_t s, int* exec)
+                        hipStream_t s, int* exec, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (nblocks <= 0) return hipSuccess;
     SWEEP_ALL(SF64)

@@ -1,5 +1,7 @@
 // Launchers of the libwdirac kernels (host side). Each returns the HIP error of the launch.
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "wd_types.hpp"
 
 namespace wd {
@@ -12,19 +14,24 @@ enum SweepOp { OP_W = 0, OP_XR = 1, OP_S = 2, OP_SHIFT = 3, OP_INIT = 4, OP_ACC 
 // x/y neighbours (1 on, 0 off, -1 the defaults hop_stage_default() / hop_stage64_default()).
 // tg: some job has temporal-gauge links (HopJob::tg); must be 0 for the adjoint hop. ntl:
 // non-temporal link loads (for launches in which no two jobs share links through L2).
+// ev0, ev1 (may be NULL): events that take the kernel's own start and end times (the launch is
+// made with them, so the interval excludes the time between launches); a launcher that has
+// nothing to launch (no blocks, no jobs) leaves them unrecorded.
 hipError_t launch_hop(int sf, int lf, bool dag, int red, int fin, const HopJob* jobs, int njobs, long nblocks,
                       SysState* sys, int gated, hipStream_t s, int* exec = nullptr, int stage = -1, int tg = 0,
-                      int ntl = 1);
+                      int ntl = 1, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Multi-RHS hop (tables whose jobs have rhs >= 2): kt = mrhs_kt(largest group), 2 or 4 systems per
 // thread at most (0: unsupported group size). Low-precision spinors only.
 int mrhs_kt(int k);
 hipError_t launch_hop_mrhs(int sf, int lf, bool dag, int red, int kt, const HopJob* jobs, int njobs, long nblocks,
-                           SysState* sys, int gated, hipStream_t s, int* exec = nullptr);
+                           SysState* sys, int gated, hipStream_t s, int* exec = nullptr, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr);
 int hop_stage_default();
 int hop_stage64_default();
-hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState* sys, int gated, hipStream_t s);
+hipError_t launch_finish(int nr, int fin, const FinJob* fins, int nfin, SysState* sys, int gated, hipStream_t s,
+                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_sweep(int op, int sfl, const SweepJob* jobs, int njobs, long nblocks, SysState* sys, int gated,
-                        hipStream_t s, int* exec = nullptr);
+                        hipStream_t s, int* exec = nullptr, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // gm (may be NULL): canonical [V][3][3] colour rotation g(n): pack stores g(n) psi(n), unpack
 // returns g(n)^dag psi'(n). nc: the internal field is in the non-chiral spin basis (pack rotates
 // into it after gamma5 and g(n), unpack out of it before them)

@@ -168,8 +168,8 @@ __global__ __launch_bounds__(BLOCK) void k_hop_mrhs(const HopJob* __restrict__ j
 
 #define MRHS_LAUNCH(SF_, LF_, DAG_, RED_, KT_)                                                                      \
     if (sf == SF_ && lf == LF_ && dag == DAG_ && red == RED_ && kt == KT_) {                                      \
-        hipLaunchKernelGGL((k_hop_mrhs<SF_, LF_, DAG_, RED_, KT_>), grid1(nblocks), dim3(BLOCK), 0, s, jobs, njobs, \
-                           sys, gated, exec);                                                                      \
+        hipExtLaunchKernelGGL((k_hop_mrhs<SF_, LF_, DAG_, RED_, KT_>), grid1(nblocks), dim3(BLOCK), 0, s, ev0, ev1, \
+                              0, jobs, njobs, sys, gated, exec);                                                   \
         return hipGetLastError();                                                                                  \
     }
 #define MRHS_REDS(SF_, LF_, KT_)                                                                                   \
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(BLOCK) void k_hop_mrhs(const HopJob* __restrict__ j
 int mrhs_kt(int k) { return k <= 2 ? 2 : k <= 4 ? 4 : 0; }
 
 hipError_t launch_hop_mrhs(int sf, int lf, bool dag, int red, int kt, const HopJob* jobs, int njobs, long nblocks,
-                           SysState* sys, int gated, hipStream_t s, int* exec)
+                           SysState* sys, int gated, hipStream_t s, int* exec, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (nblocks <= 0) return hipSuccess;
     MRHS_LINKS(SF32, 2)

@@ -234,17 +234,15 @@ template <class J>
 static void run_finish(int nr, int fin, const JobTable<J>& t, SysState* sys, int gated, hipStream_t s)
 {
     Timer& T = timer();
+    // a timed launch passes its events to the launch, which records the kernel's own start and end
+    const bool timed = T.on && !t.fin.empty();
     hipEvent_t a = nullptr, b = nullptr;
-    if (T.on) {
+    if (timed) {
         a = T.get();
         b = T.get();
-        WD_CHECK_HIP(hipEventRecord(a, s));
     }
-    WD_CHECK_HIP(launch_finish(nr, fin, t.fin_d(), (int)t.fin.size(), sys, gated, s));
-    if (T.on) {
-        WD_CHECK_HIP(hipEventRecord(b, s));
-        T.pending.push_back({TK_FINISH, a, b, 0.0, -1, 0, -1});
-    }
+    WD_CHECK_HIP(launch_finish(nr, fin, t.fin_d(), (int)t.fin.size(), sys, gated, s, a, b));
+    if (timed) T.pending.push_back({TK_FINISH, a, b, 0.0, -1, 0, -1});
 }
 
 void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>& t, SysState* sys, int gated,
@@ -254,11 +252,11 @@ void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>&
     hipEvent_t a = nullptr, b = nullptr;
     const int cls = sf == SF64 ? TK_HOP_F64 : TK_HOP_LO;
     int* flag = nullptr;
-    if (T.on) {
+    const bool timed = T.on && t.nblocks > 0;  // (a launcher with no blocks launches nothing)
+    if (timed) {
         flag = T.slot();
         a = T.get();
         b = T.get();
-        WD_CHECK_HIP(hipEventRecord(a, s));
     }
     // Non-temporal link loads keep the links from evicting the neighbour spinors in L2. They pay
     // off when the links cannot stay in the 256 MB Infinity Cache between hops anyway (more than
@@ -277,14 +275,12 @@ void run_hop(int sf, int lf, bool dag, int red, int fin, const JobTable<HopJob>&
         for (auto& j : t.host) kmax = std::max(kmax, j.ilv);
         const int kt = mrhs_kt(kmax);
         if (kt == 0 || sf == SF64) throw Error{WD_ERR_UNSUPPORTED, "multi-RHS hop: unsupported group or format"};
-        WD_CHECK_HIP(launch_hop_mrhs(sf, lf, dag, red, kt, t.d(), t.n(), t.nblocks, sys, gated, s, flag));
+        WD_CHECK_HIP(launch_hop_mrhs(sf, lf, dag, red, kt, t.d(), t.n(), t.nblocks, sys, gated, s, flag, a, b));
     } else {
-        WD_CHECK_HIP(launch_hop(sf, lf, dag, red, fin, t.d(), t.n(), t.nblocks, sys, gated, s, flag, stage, tg, ntl));
+        WD_CHECK_HIP(launch_hop(sf, lf, dag, red, fin, t.d(), t.n(), t.nblocks, sys, gated, s, flag, stage, tg, ntl, a, b));
     }
-    if (T.on) {
-        WD_CHECK_HIP(hipEventRecord(b, s));
+    if (timed)
         T.pending.push_back({cls, a, b, bytes, (int)(flag - T.dflags), t.n(), cls == TK_HOP_LO ? TK_HOP_LO_RED + red : -1});
-    }
     if (red != RED_NONE) run_finish(3, fin, t, sys, gated, s);
 }
 
@@ -293,17 +289,14 @@ void run_sweep(int op, int sfl, const JobTable<SweepJob>& t, SysState* sys, int 
     Timer& T = timer();
     hipEvent_t a = nullptr, b = nullptr;
     int* flag = nullptr;
-    if (T.on) {
+    const bool timed = T.on && t.nblocks > 0;
+    if (timed) {
         flag = T.slot();
         a = T.get();
         b = T.get();
-        WD_CHECK_HIP(hipEventRecord(a, s));
     }
-    WD_CHECK_HIP(launch_sweep(op, sfl, t.d(), t.n(), t.nblocks, sys, gated, s, flag));
-    if (T.on) {
-        WD_CHECK_HIP(hipEventRecord(b, s));
-        T.pending.push_back({TK_SWEEP, a, b, bytes, (int)(flag - T.dflags), t.n(), -1});
-    }
+    WD_CHECK_HIP(launch_sweep(op, sfl, t.d(), t.n(), t.nblocks, sys, gated, s, flag, a, b));
+    if (timed) T.pending.push_back({TK_SWEEP, a, b, bytes, (int)(flag - T.dflags), t.n(), -1});
     switch (op) {
     case OP_XR: run_finish(3, FIN_ALPHA, t, sys, gated, s); break;
     case OP_SHIFT: run_finish(0, FIN_END, t, sys, gated, s); break;  // OP_S: committed in FIN_ALPHA
